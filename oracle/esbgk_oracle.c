@@ -1,0 +1,688 @@
+/*
+ * esbgk_oracle.c -- plain, slow, FP64 CPU oracle for the polyatomic ES-BGK
+ * lattice Boltzmann scheme of Hu, Zhang, Du, Jin & Kong (arXiv:1611.02409).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference that the GPU library
+ * is checked against.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may build, load or call it.  The product
+ * (the HIP library and its Python binding) never does, and shares no code,
+ * header, table or constant generator with it.
+ *
+ * Everything is double precision and written to be read against the paper:
+ *   - lattice weights and scale r come from solving the Gauss-Hermite moment
+ *     conditions (Section VI.A, Table I; Section VI.B, Table II) by Newton's
+ *     method in long double;  D3Q39 is not in the paper and is solved from
+ *     the same kind of conditions (degree 7);
+ *   - Hermite tensors follow Grad's definition quoted in Section IV
+ *     (H^n = x^n - delta x^(n-2) + delta^2 x^(n-4) - ..., symmetrised);
+ *   - Hermite coefficients of the Gaussian follow the general-term formula
+ *     (Eq. fESCoe, Section IV): a^(n) = sum_alpha (Lambda - delta)^alpha
+ *     u^(n-2 alpha), read with Grad's symmetrised-product convention, i.e.
+ *     the sum over all ways of pairing alpha index pairs;
+ *   - the discrete target is G_i = w_i rho sum_{n<=4} a^(n).H^(n)(xi_i)/n!
+ *     (Eq. GExpansion and the definition of G_i in Section V);
+ *   - moments follow Section V (rho, rho u, rho E), the stress tensor
+ *     sigma of Eq. Lambda, Lambda of Section II (dimensionless form in
+ *     Section V) and T_rel of Section II;
+ *   - the update is collide then stream (Eqs. DiscreteReductionG and
+ *     DiscreteReductionH), periodic, with two buffers (pull streaming).
+ *
+ * Readings where the paper is ambiguous (all documented with the tests):
+ *   - relaxation rates ("reading B", default): the heat-flux rate is
+ *     omega = 1/(1/2 + (tau - 1/2)/Pr), the stress rate is 1/tau, and the
+ *     ES parameter is nu = (1 - omega_s/omega)/(1 - kappa); this reduces to
+ *     the paper's rate Pr/tau and nu = (1 - 1/Pr)/(1 - kappa) (Eq. Pr) for
+ *     large tau.  "Reading A" (omega = Pr/tau literally) is available with
+ *     reading = 1;
+ *   - the internal-energy target uses T_rel (Eq. ReductionH), not T;
+ *   - the internal-energy sum is rho e_int = sum h_i (Section II definition);
+ *   - with N_f = 0 there is no second population and T_int := T_tr.
+ *
+ * Naming: the paper's g (mass) and h (internal energy) populations are
+ * called f and g here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAXQ 40
+#define ORC_MAXD 3
+#define ORC_MAXN 6        /* highest Hermite order handled by the tensor code */
+#define ORC_MAXSHELL 9
+
+/* ------------------------------------------------------------------------ */
+/* Lattices                                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int D, Q, nshell;
+    int c[ORC_MAXQ][3];        /* integer velocity, xi_i = r * c_i            */
+    int shell_of[ORC_MAXQ];
+    int opp[ORC_MAXQ];
+    double w[ORC_MAXQ];
+    double wshell[ORC_MAXSHELL];
+    double r;
+    int maxc;                  /* largest |c| component: the streaming reach  */
+} orc_lattice;
+
+/* Shell generators (sorted absolute values).  D2Q37: Table I; D2Q33:
+ * Table II; D3Q39: the six shells 0, (1,0,0), (1,1,1), (2,0,0), (2,2,0),
+ * (3,0,0). */
+static const int SH_D2Q37[8][3] = {{0,0,0},{1,0,0},{1,1,0},{2,0,0},{2,1,0},{3,0,0},{3,1,0},{3,3,0}};
+static const int SH_D2Q33[8][3] = {{0,0,0},{1,0,0},{1,1,0},{2,0,0},{2,2,0},{3,0,0},{2,1,0},{4,4,0}};
+static const int SH_D3Q39[6][3] = {{0,0,0},{1,0,0},{1,1,1},{2,0,0},{2,2,0},{3,0,0}};
+
+/* Starting points for Newton: the printed tables (Table I, Table II) for the
+ * 2D lattices; a generic guess for D3Q39. */
+static const double GUESS_D2Q37[9] = {2.03916918e-1, 1.27544846e-1, 4.37537182e-2, 8.13659044e-3,
+                                      9.40079914e-3, 6.95051049e-4, 3.04298494e-5, 2.81093762e-5,
+                                      1.19697977 * 1.19697977};
+static const double GUESS_D2Q33[9] = {1.61987e-1, 1.43204e-1, 3.38840e-2, 5.56112e-3, 8.44799e-5,
+                                      1.13254e-3, 1.28169e-2, 3.45552e-6,
+                                      2.0 * 0.819381 * 0.819381};
+static const double GUESS_D3Q39[7] = {0.1, 0.1, 0.03, 0.01, 0.002, 0.0005, 1.3};
+
+/* Moment conditions <xi_x^2a xi_y^2b xi_z^2c> = (2a-1)!!(2b-1)!!(2c-1)!!
+ * of the unit Gaussian weight (Section IV, mu_2n = delta^n). */
+static const int COND_2D[9][3] = {{0,0,0},{1,0,0},{2,0,0},{1,1,0},{3,0,0},{2,1,0},{4,0,0},{3,1,0},{2,2,0}};
+static const int COND_3D[7][3] = {{0,0,0},{1,0,0},{2,0,0},{1,1,0},{3,0,0},{2,1,0},{1,1,1}};
+
+static long double dfact(int n) { long double v = 1; for (; n > 1; n -= 2) v *= n; return v; }
+
+static void sort3desc(int *a) {
+    for (int i = 0; i < 3; i++)
+        for (int j = i + 1; j < 3; j++)
+            if (a[j] > a[i]) { int t = a[i]; a[i] = a[j]; a[j] = t; }
+}
+
+/* Solve the dense n x n system J dx = F by Gaussian elimination with partial
+ * pivoting (long double).  Returns 0 on success. */
+static int solve_ld(int n, long double J[][10], long double *F, long double *dx) {
+    long double A[10][11];
+    for (int i = 0; i < n; i++) { for (int j = 0; j < n; j++) A[i][j] = J[i][j]; A[i][n] = F[i]; }
+    for (int k = 0; k < n; k++) {
+        int p = k;
+        for (int i = k + 1; i < n; i++) if (fabsl(A[i][k]) > fabsl(A[p][k])) p = i;
+        if (fabsl(A[p][k]) < 1e-300L) return -1;
+        if (p != k) for (int j = 0; j <= n; j++) { long double t = A[k][j]; A[k][j] = A[p][j]; A[p][j] = t; }
+        for (int i = k + 1; i < n; i++) {
+            long double m = A[i][k] / A[k][k];
+            for (int j = k; j <= n; j++) A[i][j] -= m * A[k][j];
+        }
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        long double s = A[i][n];
+        for (int j = i + 1; j < n; j++) s -= A[i][j] * dx[j];
+        dx[i] = s / A[i][i];
+    }
+    return 0;
+}
+
+/* Build a lattice: enumerate the integer velocities of each shell, then
+ * solve the moment conditions for the shell weights and x = r^2. */
+int orc_lattice_build(int D, int Q, orc_lattice *L) {
+    const int (*sh)[3]; const int (*cond)[3]; const double *guess; int nsh, ncond;
+    if (D == 2 && Q == 37) { sh = SH_D2Q37; nsh = 8; cond = COND_2D; ncond = 9; guess = GUESS_D2Q37; }
+    else if (D == 2 && Q == 33) { sh = SH_D2Q33; nsh = 8; cond = COND_2D; ncond = 9; guess = GUESS_D2Q33; }
+    else if (D == 3 && Q == 39) { sh = SH_D3Q39; nsh = 6; cond = COND_3D; ncond = 7; guess = GUESS_D3Q39; }
+    else return -1;
+    memset(L, 0, sizeof *L);
+    L->D = D; L->nshell = nsh;
+    /* enumerate velocities shell by shell */
+    int q = 0;
+    for (int s = 0; s < nsh; s++) {
+        for (int cz = (D == 3 ? -4 : 0); cz <= (D == 3 ? 4 : 0); cz++)
+            for (int cy = -4; cy <= 4; cy++)
+                for (int cx = -4; cx <= 4; cx++) {
+                    int a[3] = {abs(cx), abs(cy), abs(cz)};
+                    sort3desc(a);
+                    if (a[0] == sh[s][0] && a[1] == sh[s][1] && a[2] == sh[s][2]) {
+                        if (q >= ORC_MAXQ) return -2;
+                        L->c[q][0] = cx; L->c[q][1] = cy; L->c[q][2] = cz;
+                        L->shell_of[q] = s; q++;
+                    }
+                }
+    }
+    if (q != Q) return -3;
+    L->Q = Q;
+    for (int i = 0; i < Q; i++) {
+        L->opp[i] = -1;
+        for (int j = 0; j < Q; j++)
+            if (L->c[j][0] == -L->c[i][0] && L->c[j][1] == -L->c[i][1] && L->c[j][2] == -L->c[i][2]) L->opp[i] = j;
+        for (int d = 0; d < D; d++) if (abs(L->c[i][d]) > L->maxc) L->maxc = abs(L->c[i][d]);
+    }
+    /* M[k][s] = sum over the velocities of shell s of c_x^2a c_y^2b c_z^2c */
+    long double M[10][10] = {{0}}; int deg[10];
+    for (int k = 0; k < ncond; k++) {
+        deg[k] = cond[k][0] + cond[k][1] + cond[k][2];
+        for (int i = 0; i < Q; i++) {
+            long double m = 1;
+            for (int d = 0; d < 3; d++) for (int e = 0; e < 2 * cond[k][d]; e++) m *= L->c[i][d];
+            M[k][L->shell_of[i]] += m;
+        }
+    }
+    long double x[10], tgt[10];
+    for (int k = 0; k < ncond; k++) tgt[k] = dfact(2 * cond[k][0] - 1) * dfact(2 * cond[k][1] - 1) * dfact(2 * cond[k][2] - 1);
+    for (int s = 0; s <= nsh; s++) x[s] = guess[s];
+    int n = nsh + 1;
+    for (int it = 0; it < 200; it++) {
+        long double F[10], J[10][10], dx[10], X = x[nsh];
+        for (int k = 0; k < ncond; k++) {
+            long double sw = 0;
+            for (int s = 0; s < nsh; s++) sw += M[k][s] * x[s];
+            long double Xd = powl(X, deg[k]);
+            F[k] = sw * Xd - tgt[k];
+            for (int s = 0; s < nsh; s++) J[k][s] = M[k][s] * Xd;
+            J[k][nsh] = deg[k] ? sw * deg[k] * powl(X, deg[k] - 1) : 0;
+        }
+        if (solve_ld(n, J, F, dx)) return -4;
+        long double step = 0;
+        for (int s = 0; s < n; s++) { x[s] -= dx[s]; step = fmaxl(step, fabsl(dx[s])); }
+        if (step < 1e-19L && it > 3) break;
+    }
+    for (int s = 0; s < nsh; s++) { if (!(x[s] > 0)) return -5; L->wshell[s] = (double)x[s]; }
+    if (!(x[nsh] > 0)) return -5;
+    L->r = (double)sqrtl(x[nsh]);
+    for (int i = 0; i < Q; i++) L->w[i] = L->wshell[L->shell_of[i]];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Hermite tensors and coefficients (Section IV)                            */
+/* ------------------------------------------------------------------------ */
+
+/* A partial pairing of the index positions {0..n-1}: mate[p] = partner of p,
+ * or -1 if p is unpaired.  All partial pairings are enumerated recursively. */
+typedef struct { int n, count; signed char mate[800][ORC_MAXN]; } pairing_set;
+
+static void enum_pairings(pairing_set *ps, signed char *mate, int n) {
+    int p = -2;
+    for (int i = 0; i < n; i++) if (mate[i] == -2) { p = i; break; }
+    if (p < 0) { memcpy(ps->mate[ps->count++], mate, (size_t)n); return; }
+    mate[p] = -1;                           /* p stays single */
+    enum_pairings(ps, mate, n);
+    for (int q = p + 1; q < n; q++) {       /* or p pairs with a later free q */
+        if (mate[q] != -2) continue;
+        mate[p] = (signed char)q; mate[q] = (signed char)p;
+        enum_pairings(ps, mate, n);
+        mate[q] = -2;
+    }
+    mate[p] = -2;
+}
+
+static pairing_set PAIRINGS[ORC_MAXN + 1];
+static int pairings_ready = 0;
+
+static void init_pairings(void) {
+    if (pairings_ready) return;
+    for (int n = 0; n <= ORC_MAXN; n++) {
+        signed char mate[ORC_MAXN];
+        for (int i = 0; i < n; i++) mate[i] = -2;
+        PAIRINGS[n].n = n; PAIRINGS[n].count = 0;
+        enum_pairings(&PAIRINGS[n], mate, n);
+    }
+    pairings_ready = 1;
+}
+
+static int ipow(int b, int e) { int v = 1; while (e-- > 0) v *= b; return v; }
+
+/* index tuple (i_1..i_n) of the flat position k in a rank-n tensor, base D,
+ * first index fastest */
+static void unflatten(int k, int n, int D, int *idx) { for (int p = 0; p < n; p++) { idx[p] = k % D; k /= D; } }
+
+/* Grad's Hermite tensor H^(n)(xi): sum over partial pairings of
+ * (-1)^(#pairs) prod_pairs delta prod_singles xi. */
+void orc_hermite(int n, int D, const double *xi, double *out) {
+    init_pairings();
+    int N = ipow(D, n), idx[ORC_MAXN];
+    for (int k = 0; k < N; k++) {
+        unflatten(k, n, D, idx);
+        double s = 0;
+        for (int t = 0; t < PAIRINGS[n].count; t++) {
+            const signed char *m = PAIRINGS[n].mate[t];
+            double term = 1; int npairs = 0;
+            for (int p = 0; p < n && term != 0; p++) {
+                if (m[p] < 0) term *= xi[idx[p]];
+                else if (m[p] > p) { npairs++; if (idx[p] != idx[m[p]]) term = 0; }
+            }
+            s += (npairs & 1) ? -term : term;
+        }
+        out[k] = s;
+    }
+}
+
+/* General-term Hermite coefficient a^(n) of the Gaussian with mean u and
+ * covariance Lambda = A + delta (Eq. fESCoe): the sum over all partial
+ * pairings of the n index positions of prod_pairs A_{ab} prod_singles u_c.
+ *
+ * The pairings are expanded once into a term table: every term of every
+ * component is a list of factor slots into v = (u_0..u_{D-1}, A_00..A_{DD}),
+ * so evaluating a^(n) is a plain sum of products. */
+typedef struct { int nterm[729]; int start[729]; int nfac[800 * 729 / 8]; short fac[800 * 729 / 8][ORC_MAXN]; } coeff_table;
+static coeff_table *CTAB[ORC_MAXD + 1][ORC_MAXN + 1];
+
+static const coeff_table *coeff_table_get(int n, int D) {
+    if (CTAB[D][n]) return CTAB[D][n];
+    init_pairings();
+    coeff_table *t = (coeff_table *)calloc(1, sizeof *t);
+    int N = ipow(D, n), idx[ORC_MAXN], pos = 0;
+    for (int k = 0; k < N; k++) {
+        unflatten(k, n, D, idx);
+        t->start[k] = pos; t->nterm[k] = PAIRINGS[n].count;
+        for (int s = 0; s < PAIRINGS[n].count; s++, pos++) {
+            const signed char *m = PAIRINGS[n].mate[s];
+            int nf = 0;
+            for (int p = 0; p < n; p++) {
+                if (m[p] < 0) t->fac[pos][nf++] = (short)idx[p];                          /* u_c     */
+                else if (m[p] > p) t->fac[pos][nf++] = (short)(D + idx[p] * D + idx[m[p]]); /* A_{ab} */
+            }
+            t->nfac[pos] = nf;
+        }
+    }
+    CTAB[D][n] = t;
+    return t;
+}
+
+static void coeff_eval(const coeff_table *t, int n, int D, const double *v, double *out) {
+    int N = ipow(D, n);
+    for (int k = 0; k < N; k++) {
+        double s = 0;
+        for (int e = t->start[k]; e < t->start[k] + t->nterm[k]; e++) {
+            double term = 1;
+            for (int f = 0; f < t->nfac[e]; f++) term *= v[t->fac[e][f]];
+            s += term;
+        }
+        out[k] = s;
+    }
+}
+
+void orc_coeff(int n, int D, const double *u, const double *A, double *out) {
+    double v[ORC_MAXD + ORC_MAXD * ORC_MAXD];
+    for (int a = 0; a < D; a++) v[a] = u[a];
+    for (int a = 0; a < D * D; a++) v[D + a] = A[a];
+    coeff_eval(coeff_table_get(n, D), n, D, v, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete Gaussian target                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    orc_lattice L;
+    int order;                                  /* Hermite truncation order, 4 */
+    double xi[ORC_MAXQ][3];
+    /* Hn[n][k*Q + i] = component k of H^(n)(xi_i): the direction index runs
+     * fastest so that one coefficient component meets all directions */
+    double *Hn[ORC_MAXN + 1];
+} orc_basis;
+
+static int basis_init(orc_basis *B, int D, int Q, int order) {
+    memset(B, 0, sizeof *B);
+    int rc = orc_lattice_build(D, Q, &B->L);
+    if (rc) return rc;
+    if (order < 0 || order > ORC_MAXN) return -6;
+    B->order = order;
+    for (int n = 0; n <= order; n++) coeff_table_get(n, D);
+    double h[729];
+    for (int n = 0; n <= order; n++) {
+        B->Hn[n] = (double *)malloc(sizeof(double) * (size_t)ipow(D, n) * Q);
+        if (!B->Hn[n]) return -7;
+    }
+    for (int i = 0; i < Q; i++) {
+        for (int d = 0; d < D; d++) B->xi[i][d] = B->L.r * B->L.c[i][d];
+        for (int n = 0; n <= order; n++) {
+            orc_hermite(n, D, B->xi[i], h);
+            for (int k = 0; k < ipow(D, n); k++) B->Hn[n][k * Q + i] = h[k];
+        }
+    }
+    return 0;
+}
+
+static void basis_free(orc_basis *B) {
+    for (int n = 0; n <= ORC_MAXN; n++) { free(B->Hn[n]); B->Hn[n] = NULL; }
+}
+
+/* G_i = w_i rho sum_{n<=order} (1/n!) a^(n) : H^(n)(xi_i).  For every
+ * direction the contraction a^(n):H^(n) is summed over the components k in
+ * ascending order; the loop over directions is innermost. */
+static void basis_target(const orc_basis *B, double rho, const double *u, const double *A, double *G) {
+    int D = B->L.D, Q = B->L.Q;
+    double a[729], s[ORC_MAXQ], c[ORC_MAXQ], nfact = 1;
+    for (int i = 0; i < Q; i++) s[i] = 0;
+    for (int n = 0; n <= B->order; n++) {
+        if (n > 0) nfact *= n;
+        orc_coeff(n, D, u, A, a);
+        int N = ipow(D, n);
+        for (int i = 0; i < Q; i++) c[i] = 0;
+        for (int k = 0; k < N; k++) {
+            const double ak = a[k], *h = B->Hn[n] + (size_t)k * Q;
+            for (int i = 0; i < Q; i++) c[i] += ak * h[i];
+        }
+        for (int i = 0; i < Q; i++) s[i] += c[i] / nfact;
+    }
+    for (int i = 0; i < Q; i++) G[i] = B->L.w[i] * rho * s[i];
+}
+
+/* Stand-alone target for tests: G_i(rho, u, A) with the order-4 truncation. */
+int orc_equilibrium(int D, int Q, double rho, const double *u, const double *A, double *G) {
+    orc_basis B;
+    int rc = basis_init(&B, D, Q, 4);
+    if (!rc) basis_target(&B, rho, u, A, G);
+    basis_free(&B);
+    return rc;
+}
+
+int orc_equilibrium_order(int D, int Q, int order, double rho, const double *u, const double *A, double *G) {
+    orc_basis B;
+    int rc = basis_init(&B, D, Q, order);
+    if (!rc) basis_target(&B, rho, u, A, G);
+    basis_free(&B);
+    return rc;
+}
+
+/* Lattice export for tests: c[Q*3], w[Q], r, opp[Q]. */
+int orc_lattice_export(int D, int Q, int *c, double *w, double *r, int *opp) {
+    orc_lattice L;
+    int rc = orc_lattice_build(D, Q, &L);
+    if (rc) return rc;
+    for (int i = 0; i < Q; i++) {
+        for (int d = 0; d < 3; d++) c[3 * i + d] = L.c[i][d];
+        w[i] = L.w[i]; opp[i] = L.opp[i];
+    }
+    *r = L.r;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parameters                                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double omega, omega_s, nu, kappa, gamma, Pr, tau; int Nf; } orc_params;
+
+/* out = {omega, omega_s, nu, gamma}.  reading 0 = B (default), 1 = A. */
+int orc_param_map(int D, int Nf, double Pr, double tau, double kappa, int reading, double *out) {
+    if (!(tau > 0.5) || !(Pr > 0) || Nf < 0 || !(kappa >= 0 && kappa < 1)) return -1;
+    double omega, omega_s, nu;
+    if (reading == 0) {
+        omega_s = 1.0 / tau;
+        omega = 1.0 / (0.5 + (tau - 0.5) / Pr);
+        nu = (1.0 - omega_s / omega) / (1.0 - kappa);
+    } else {
+        omega = Pr / tau;                       /* Eq. DiscreteReductionG literally */
+        nu = (1.0 - 1.0 / Pr) / (1.0 - kappa);  /* from Eq. Pr */
+        omega_s = omega * (1.0 - (1.0 - kappa) * nu);
+    }
+    out[0] = omega; out[1] = omega_s; out[2] = nu;
+    out[3] = (double)(Nf + D + 2) / (double)(Nf + D);   /* Eq. Gamma */
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One-cell collision (Section V)                                           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double rho, u[3], sigma[9], Ttr, Tint, Teq, Trel, Lambda[9];
+} orc_cell_moments;
+
+/* Moments of the pre-collision populations of one cell. */
+static void cell_moments(const orc_basis *B, const orc_params *p, const double *f, const double *g,
+                         orc_cell_moments *m) {
+    int D = B->L.D, Q = B->L.Q;
+    double rho = 0, j[3] = {0, 0, 0}, P[9] = {0};
+    for (int i = 0; i < Q; i++) {
+        rho += f[i];
+        for (int a = 0; a < D; a++) {
+            j[a] += B->xi[i][a] * f[i];
+            for (int b = 0; b < D; b++) P[a * D + b] += B->xi[i][a] * B->xi[i][b] * f[i];
+        }
+    }
+    m->rho = rho;
+    for (int a = 0; a < D; a++) m->u[a] = j[a] / rho;
+    double tr = 0;
+    for (int a = 0; a < D; a++)
+        for (int b = 0; b < D; b++) {
+            m->sigma[a * D + b] = P[a * D + b] / rho - m->u[a] * m->u[b];   /* Eq. Lambda */
+            if (a == b) tr += m->sigma[a * D + b];
+        }
+    m->Ttr = tr / D;                                   /* e_tr = (D/2) T_tr */
+    if (p->Nf > 0) {
+        double sg = 0;
+        for (int i = 0; i < Q; i++) sg += g[i];
+        m->Tint = 2.0 * sg / (p->Nf * rho);            /* rho e_int = sum h_i, e_int = (N_f/2) T_int */
+    } else {
+        m->Tint = m->Ttr;
+    }
+    m->Teq = (D * m->Ttr + p->Nf * m->Tint) / (D + p->Nf);
+    m->Trel = p->kappa * m->Teq + (1.0 - p->kappa) * m->Tint;
+    for (int a = 0; a < D; a++)
+        for (int b = 0; b < D; b++)
+            m->Lambda[a * D + b] = (1.0 - p->kappa) * ((a == b ? (1.0 - p->nu) * m->Ttr : 0.0) + p->nu * m->sigma[a * D + b])
+                                 + (a == b ? p->kappa * m->Teq : 0.0);
+}
+
+/* Collide one cell: f, g (pre-collision) -> fo, go (post-collision). */
+static void cell_collide(const orc_basis *B, const orc_params *p, const double *f, const double *g,
+                         double *fo, double *go) {
+    int D = B->L.D, Q = B->L.Q;
+    orc_cell_moments m;
+    cell_moments(B, p, f, g, &m);
+    double A[9], G[ORC_MAXQ];
+    for (int a = 0; a < D; a++) for (int b = 0; b < D; b++) A[a * D + b] = m.Lambda[a * D + b] - (a == b ? 1.0 : 0.0);
+    basis_target(B, m.rho, m.u, A, G);
+    for (int i = 0; i < Q; i++) {
+        fo[i] = f[i] - p->omega * (f[i] - G[i]);
+        if (p->Nf > 0) go[i] = g[i] - p->omega * (g[i] - 0.5 * p->Nf * m.Trel * G[i]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Periodic simulation with two buffers                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    orc_basis B;
+    orc_params p;
+    int64_t n[3], ncell;
+    int npop;                      /* 1 (N_f = 0) or 2 */
+    double *cur, *nxt;             /* [cell][pop][Q] */
+    int64_t steps;
+} orc_sim;
+
+/* periodic wrap of a coordinate displaced by at most a few cells */
+static int64_t wrap(int64_t x, int64_t n) {
+    while (x < 0) x += n;
+    while (x >= n) x -= n;
+    return x;
+}
+
+static int64_t cell_index(const orc_sim *s, int64_t x, int64_t y, int64_t z) {
+    return (wrap(z, s->n[2]) * s->n[1] + wrap(y, s->n[1])) * s->n[0] + wrap(x, s->n[0]);
+}
+
+void orc_sim_destroy(orc_sim *s) {
+    if (!s) return;
+    basis_free(&s->B);
+    free(s->cur); free(s->nxt); free(s);
+}
+
+orc_sim *orc_sim_create(int D, int Q, int Nf, double Pr, double tau, double kappa, int reading, const int64_t *dims) {
+    double pm[4];
+    if (orc_param_map(D, Nf, Pr, tau, kappa, reading, pm)) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof *s);
+    if (!s) return NULL;
+    if (basis_init(&s->B, D, Q, 4)) { orc_sim_destroy(s); return NULL; }
+    s->p.omega = pm[0]; s->p.omega_s = pm[1]; s->p.nu = pm[2]; s->p.gamma = pm[3];
+    s->p.kappa = kappa; s->p.Pr = Pr; s->p.tau = tau; s->p.Nf = Nf;
+    s->n[0] = s->n[1] = s->n[2] = 1;
+    s->ncell = 1;
+    for (int d = 0; d < D; d++) { if (dims[d] < 1) { orc_sim_destroy(s); return NULL; } s->n[d] = dims[d]; s->ncell *= dims[d]; }
+    s->npop = Nf > 0 ? 2 : 1;
+    size_t bytes = sizeof(double) * (size_t)s->ncell * (size_t)s->npop * (size_t)Q;
+    s->cur = (double *)malloc(bytes); s->nxt = (double *)malloc(bytes);
+    if (!s->cur || !s->nxt) { orc_sim_destroy(s); return NULL; }
+    return s;
+}
+
+/* Equilibrium start from (rho, u, T): f_i = G_i(rho, u, Lambda = T delta),
+ * g_i = (N_f/2) T G_i.  Fields are row-major with x fastest; u holds D
+ * planes. */
+void orc_sim_init(orc_sim *s, const double *rho, const double *u, const double *T) {
+    int D = s->B.L.D, Q = s->B.L.Q;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < s->ncell; k++) {
+        double uu[3] = {0, 0, 0}, A[9] = {0}, G[ORC_MAXQ];
+        for (int a = 0; a < D; a++) { uu[a] = u[a * s->ncell + k]; A[a * D + a] = T[k] - 1.0; }
+        basis_target(&s->B, rho[k], uu, A, G);
+        double *c = s->cur + (size_t)k * s->npop * Q;
+        for (int i = 0; i < Q; i++) {
+            c[i] = G[i];
+            if (s->npop == 2) c[Q + i] = 0.5 * s->p.Nf * T[k] * G[i];
+        }
+    }
+    s->steps = 0;
+}
+
+/* One step: collide every cell in place, then pull-stream into the second
+ * buffer (f_i(x, t+1) = f_i*(x - c_i, t)), periodic in every axis. */
+void orc_sim_step(orc_sim *s, int64_t nsteps) {
+    int Q = s->B.L.Q, np = s->npop;
+    for (int64_t t = 0; t < nsteps; t++) {
+        #pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < s->ncell; k++) {
+            double *c = s->cur + (size_t)k * np * Q;
+            double fo[ORC_MAXQ], go[ORC_MAXQ];
+            cell_collide(&s->B, &s->p, c, np == 2 ? c + Q : NULL, fo, go);
+            memcpy(c, fo, sizeof(double) * Q);
+            if (np == 2) memcpy(c + Q, go, sizeof(double) * Q);
+        }
+        #pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < s->ncell; k++) {
+            int64_t x = k % s->n[0], y = (k / s->n[0]) % s->n[1], z = k / (s->n[0] * s->n[1]);
+            double *dst = s->nxt + (size_t)k * np * Q;
+            for (int i = 0; i < Q; i++) {
+                int64_t src = cell_index(s, x - s->B.L.c[i][0], y - s->B.L.c[i][1], z - s->B.L.c[i][2]);
+                for (int pp = 0; pp < np; pp++) dst[pp * Q + i] = s->cur[(size_t)src * np * Q + pp * Q + i];
+            }
+        }
+        double *tmp = s->cur; s->cur = s->nxt; s->nxt = tmp;
+        s->steps++;
+    }
+}
+
+/* Pre-collision moments at the current step: rho, u (D planes), T = T_eq,
+ * and optionally the central pressure tensor rho*sigma as D(D+1)/2 planes
+ * (xx, xy, yy) or (xx, xy, xz, yy, yz, zz).  Any output may be NULL. */
+void orc_sim_moments(const orc_sim *s, double *rho, double *u, double *T, double *P) {
+    int D = s->B.L.D, Q = s->B.L.Q, np = s->npop;
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < s->ncell; k++) {
+        const double *c = s->cur + (size_t)k * np * Q;
+        orc_cell_moments m;
+        cell_moments(&s->B, &s->p, c, np == 2 ? c + Q : NULL, &m);
+        if (rho) rho[k] = m.rho;
+        if (u) for (int a = 0; a < D; a++) u[a * s->ncell + k] = m.u[a];
+        if (T) T[k] = m.Teq;
+        if (P) {
+            int q = 0;
+            for (int a = 0; a < D; a++) for (int b = a; b < D; b++) P[(q++) * s->ncell + k] = m.rho * m.sigma[a * D + b];
+        }
+    }
+}
+
+/* Domain totals in FP64, summed in cell order: {mass, momentum[D], energy},
+ * energy = sum (1/2 xi^2 f + g) (Section V, Eq. TransEnergy). */
+void orc_sim_totals(const orc_sim *s, double *out) {
+    int D = s->B.L.D, Q = s->B.L.Q, np = s->npop;
+    double mass = 0, mom[3] = {0, 0, 0}, en = 0;
+    for (int64_t k = 0; k < s->ncell; k++) {
+        const double *c = s->cur + (size_t)k * np * Q;
+        for (int i = 0; i < Q; i++) {
+            double xi2 = 0;
+            for (int a = 0; a < D; a++) { mom[a] += s->B.xi[i][a] * c[i]; xi2 += s->B.xi[i][a] * s->B.xi[i][a]; }
+            mass += c[i];
+            en += 0.5 * xi2 * c[i];
+            if (np == 2) en += c[Q + i];
+        }
+    }
+    out[0] = mass;
+    for (int a = 0; a < D; a++) out[1 + a] = mom[a];
+    out[1 + D] = en;
+}
+
+/* Raw populations in natural layout: f[i*ncell + k], g likewise. */
+void orc_sim_get_pops(const orc_sim *s, double *f, double *g) {
+    int Q = s->B.L.Q, np = s->npop;
+    for (int64_t k = 0; k < s->ncell; k++)
+        for (int i = 0; i < Q; i++) {
+            f[(size_t)i * s->ncell + k] = s->cur[(size_t)k * np * Q + i];
+            if (np == 2 && g) g[(size_t)i * s->ncell + k] = s->cur[(size_t)k * np * Q + Q + i];
+        }
+}
+
+void orc_sim_set_pops(orc_sim *s, const double *f, const double *g) {
+    int Q = s->B.L.Q, np = s->npop;
+    for (int64_t k = 0; k < s->ncell; k++)
+        for (int i = 0; i < Q; i++) {
+            s->cur[(size_t)k * np * Q + i] = f[(size_t)i * s->ncell + k];
+            if (np == 2) s->cur[(size_t)k * np * Q + Q + i] = g[(size_t)i * s->ncell + k];
+        }
+}
+
+int64_t orc_sim_steps(const orc_sim *s) { return s->steps; }
+
+/* Parameters actually in use: {omega, omega_s, nu, gamma, kappa}. */
+void orc_sim_params(const orc_sim *s, double *out) {
+    out[0] = s->p.omega; out[1] = s->p.omega_s; out[2] = s->p.nu; out[3] = s->p.gamma; out[4] = s->p.kappa;
+}
+
+/* Post-collision populations of single cells, independent of any domain:
+ * fin/gin hold n cells of Q values each; fout/gout receive the collided
+ * values.  Used to check one step of a large GPU run at sampled cells. */
+int orc_collide_cells(int D, int Q, int Nf, double Pr, double tau, double kappa, int reading, int64_t n,
+                      const double *fin, const double *gin, double *fout, double *gout) {
+    double pm[4];
+    if (orc_param_map(D, Nf, Pr, tau, kappa, reading, pm)) return -1;
+    orc_basis B;
+    int rc = basis_init(&B, D, Q, 4);
+    if (rc) { basis_free(&B); return rc; }
+    orc_params p = {pm[0], pm[1], pm[2], kappa, pm[3], Pr, tau, Nf};
+    #pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; k++)
+        cell_collide(&B, &p, fin + k * Q, Nf > 0 ? gin + k * Q : NULL, fout + k * Q, Nf > 0 ? gout + k * Q : NULL);
+    basis_free(&B);
+    return 0;
+}
+
+/* Moments of single cells from raw populations: out[k*(4+D(D+1)/2)] =
+ * {rho, u[D], T_eq, rho*sigma (upper triangle)} -- padded to 3 u slots. */
+int orc_cell_moments_many(int D, int Q, int Nf, double kappa, int64_t n, const double *fin, const double *gin,
+                          double *out) {
+    orc_basis B;
+    int rc = basis_init(&B, D, Q, 0);
+    if (rc) { basis_free(&B); return rc; }
+    orc_params p; memset(&p, 0, sizeof p); p.Nf = Nf; p.kappa = kappa;
+    for (int64_t k = 0; k < n; k++) {
+        orc_cell_moments m;
+        cell_moments(&B, &p, fin + k * Q, Nf > 0 ? gin + k * Q : NULL, &m);
+        double *o = out + k * 11;
+        o[0] = m.rho; o[1] = m.u[0]; o[2] = m.u[1]; o[3] = m.u[2]; o[4] = m.Teq;
+        int q = 5;
+        for (int a = 0; a < D; a++) for (int b = a; b < D; b++) o[q++] = m.rho * m.sigma[a * D + b];
+    }
+    basis_free(&B);
+    return 0;
+}
+
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n; return 1;
+#endif
+}
