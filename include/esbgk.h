@@ -1,0 +1,237 @@
+/*
+ * esbgk.h -- C ABI of the MI355X (gfx950) ES-BGK lattice Boltzmann library.
+ *
+ * The library advances the two-population lattice Boltzmann scheme with a
+ * polyatomic ellipsoidal-statistical (ES-BGK) Gaussian target of Hu, Zhang,
+ * Du, Jin and Kong, "A lattice Boltzmann scheme with arbitrary Prandtl number
+ * and specific heat ratio based on the polyatomic ES-BGK model"
+ * (arXiv:1611.02409):
+ *
+ *   - populations f_i (mass, the paper's g_i) and g_i (internal energy, the
+ *     paper's h_i), Section III and the discrete definitions of Section V;
+ *   - per cell, the moments rho, rho u, the stress tensor sigma (Eq. Lambda),
+ *     T_tr, T_int, T_eq and T_rel (Sections II and V);
+ *   - the target G_i = w_i rho sum_{n<=4} a^(n).H^(n)(xi_i)/n! whose Hermite
+ *     coefficients come from the general-term formula (Eq. fESCoe, Eq.
+ *     GExpansion) with Lambda of Section II;
+ *   - collide and stream (Eqs. DiscreteReductionG and DiscreteReductionH),
+ *     f_i <- f_i - omega (f_i - G_i), g_i <- g_i - omega (g_i - N_f/2 T_rel G_i),
+ *     on a periodic grid.
+ *
+ * Conventions shared by every entry point
+ *   Units: the paper's dimensionless thermal units (Section V): rho0 = T0 = 1,
+ *     velocities in units of sqrt(R_g T0).  The lattice velocity of direction
+ *     i is xi_i = r c_i with integer c_i; one step moves c_i cells.
+ *   Lattices: (D, Q) = (2, 37) Table I; (2, 33) Table II; (3, 39) (three-
+ *     dimensional, not in the paper; six shells solved from the degree-7
+ *     Gauss-Hermite conditions).
+ *   Parameters: tau > 1/2 is the relaxation time in steps, Pr > 0 the
+ *     Prandtl number, N_f >= 0 the extra degrees of freedom, so that
+ *     gamma = (N_f + D + 2)/(N_f + D) (Eq. Gamma).  The stress relaxes at
+ *     1/tau and the heat flux at omega = 1/(1/2 + (tau - 1/2)/Pr); the ES
+ *     parameter is nu = (1 - omega_s/omega)/(1 - kappa), which reproduces
+ *     Eq. Pr exactly for the lattice transport coefficients (kinematic
+ *     viscosity (T/r^2)(tau - 1/2), thermal diffusivity that over Pr, in grid
+ *     units) and the paper's rate Pr/tau for large tau.  kappa defaults to
+ *     0.2 (Section VI.A).
+ *   Fields: host arrays of doubles, row-major with x fastest; a field has
+ *     ncell = nx*ny(*nz) values; vector fields (u) hold D such planes in the
+ *     order x, y(, z); the pressure tensor holds D(D+1)/2 planes in the order
+ *     xx, xy, yy (2D) or xx, xy, xz, yy, yz, zz (3D).
+ *   Storage: ESBGK_F32 keeps each population as an FP32 deviation from its
+ *     rest-state value; ESBGK_F16_DEV and ESBGK_BF16_DEV keep it as an FP16 or
+ *     BF16 deviation multiplied by a per-direction power of two near 1/w_i.
+ *     Collision arithmetic is FP32 in all modes.
+ *   Errors: every int-returning call returns ESBGK_OK (0) or a negative code
+ *     below and sets a thread-local message (esbgk_last_error).  No call
+ *     throws or aborts.  A failing call leaves the handle usable unless it
+ *     says otherwise.
+ *   Threads and streams: a handle is not thread-safe; distinct handles are
+ *     independent.  Kernel launches go to the handle's HIP stream; calls
+ *     documented as asynchronous return before the GPU has finished.
+ */
+#ifndef ESBGK_H
+#define ESBGK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ESBGK_OK 0
+#define ESBGK_EINVAL (-1)        /* bad argument                                */
+#define ESBGK_EUNSUPPORTED (-2)  /* lattice / storage / size not supported      */
+#define ESBGK_ENOMEM (-3)        /* device or host allocation failed            */
+#define ESBGK_EDEVICE (-4)       /* a HIP call failed                           */
+#define ESBGK_ESTATE (-5)        /* call not valid in the handle's state        */
+#define ESBGK_ENONFINITE (-6)    /* non-finite input or result                  */
+#define ESBGK_EIO (-7)           /* checkpoint file error                       */
+
+#define ESBGK_F32 0
+#define ESBGK_F16_DEV 1
+#define ESBGK_BF16_DEV 2
+
+typedef struct esbgk_lattice esbgk_t;
+typedef struct esbgk_batch esbgk_batch_t;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *esbgk_last_error(void);
+
+/* Library version string. */
+const char *esbgk_version(void);
+
+/* Lattice constants as the library uses them (FP64): c[3*Q] integer
+ * velocities (unused components 0), w[Q] weights, *r scale factor,
+ * *reach the largest |c| component.  Population i of the library's storage
+ * is direction i of this list.  Any output may be NULL.  Section VI
+ * (Tables I, II) and the three-dimensional D3Q39 set. */
+int esbgk_lattice_info(int D, int Q, int *c, double *w, double *r, int *reach);
+
+/* Relaxation parameters the library derives from (D, N_f, Pr, tau, kappa):
+ * out[0] omega (heat-flux rate), out[1] omega_s (stress rate, 1/tau),
+ * out[2] nu (ES parameter of Lambda), out[3] gamma (Eq. Gamma).
+ * ESBGK_EINVAL if tau <= 1/2, Pr <= 0, N_f < 0, kappa outside [0, 1) or if
+ * Lambda could lose positive-definiteness for some admissible stress. */
+int esbgk_params(int D, int N_f, double Pr, double tau, double kappa, double out[4]);
+
+/* Create a periodic lattice of dims[0] x dims[1] (x dims[2]) cells.
+ * Requires every dim >= the lattice reach and cells per population plane
+ * small enough that a plane fits in 4 GiB.  The library allocates the
+ * population storage (2 Q planes, or Q when N_f = 0) and owns it; work goes
+ * to the default HIP stream until esbgk_set_stream.  The handle starts
+ * without a state: call esbgk_init_fields before stepping. */
+int esbgk_create(int D, int Q, int N_f, double Pr, double tau, const int64_t *dims, int storage, esbgk_t **out);
+
+/* As esbgk_create, but the populations live in caller-owned device memory
+ * dev_buf of at least esbgk_storage_bytes() bytes (256-byte aligned), and
+ * work goes to hip_stream (a hipStream_t, or NULL for the default stream).
+ * The library never frees dev_buf; it must outlive the handle. */
+int esbgk_create_ex(int D, int Q, int N_f, double Pr, double tau, const int64_t *dims, int storage,
+                    void *dev_buf, size_t bytes, void *hip_stream, esbgk_t **out);
+
+/* Bytes of population storage a lattice of this shape needs. */
+int esbgk_storage_bytes(int D, int Q, int N_f, const int64_t *dims, int storage, size_t *bytes);
+
+/* Set kappa (0 <= kappa < 1; the Section II blend of T_eq into Lambda and
+ * T_rel) and re-derive nu.  Allowed at any time; applies to later steps. */
+int esbgk_set_kappa(esbgk_t *h, double kappa);
+
+/* Route later work to hip_stream (NULL: default stream).  The caller keeps
+ * ownership of the stream. */
+int esbgk_set_stream(esbgk_t *h, void *hip_stream);
+
+/* Write the equilibrium state of host fields rho (> 0), u (D planes) and
+ * T (> 0): f_i = G_i(rho, u, Lambda = T delta), g_i = (N_f/2) T G_i.
+ * Resets the step counter to 0.  Synchronous.  ESBGK_ENONFINITE or
+ * ESBGK_EINVAL for non-finite or non-positive rho or T. */
+int esbgk_init_fields(esbgk_t *h, const double *rho, const double *u, const double *T);
+
+/* Enqueue n >= 0 collide-and-stream steps (asynchronous).  ESBGK_ESTATE
+ * before init. */
+int esbgk_step(esbgk_t *h, int64_t n);
+
+/* Steps taken since init (or loaded from a checkpoint). */
+int esbgk_step_count(const esbgk_t *h, int64_t *n);
+
+/* Pre-collision moments at the current step (Section V): rho, u (D planes),
+ * T = T_eq, and, if P is not NULL, the central pressure tensor
+ * rho sigma (D(D+1)/2 planes).  Any output may be NULL.  Synchronous. */
+int esbgk_read_moments(esbgk_t *h, double *rho, double *u, double *T, double *P);
+
+/* Domain totals in FP64: out[0] mass, out[1..D] momentum, out[D+1] total
+ * energy sum(1/2 xi^2 f + g) (Section V).  Reduced on the GPU in FP64.
+ * Synchronous. */
+int esbgk_totals(esbgk_t *h, double *out);
+
+/* Populations of n listed cells (flat indices, x fastest) at the current
+ * step, decoded to FP64: f[k*Q + i], g[k*Q + i] (g may be NULL; ignored when
+ * N_f = 0).  Synchronous.  For checks of single cells of large runs. */
+int esbgk_read_cells(esbgk_t *h, int64_t n, const int64_t *cells, double *f, double *g);
+
+/* All populations at the current step, decoded to FP64, as Q planes of
+ * ncell values: f[i*ncell + k] (g likewise, may be NULL).  Synchronous. */
+int esbgk_read_populations(esbgk_t *h, double *f, double *g);
+
+/* Overwrite all populations from FP64 planes laid out as in
+ * esbgk_read_populations (g ignored when N_f = 0); keeps the step counter.
+ * Values are encoded in the handle's storage mode.  Synchronous. */
+int esbgk_write_populations(esbgk_t *h, const double *f, const double *g);
+
+/* Checkpoint the raw state (storage, parameters, step counter) to a file /
+ * restore it into a handle created with the same lattice, dims, N_f and
+ * storage.  Synchronous.  ESBGK_EIO on file errors, ESBGK_EINVAL on a
+ * mismatching handle. */
+int esbgk_save(esbgk_t *h, const char *path);
+int esbgk_load(esbgk_t *h, const char *path);
+
+/* Time n steps on the handle's stream with HIP events around each launch:
+ * *total_ms is the elapsed time of the n launches, per_launch_ms (if not
+ * NULL, n entries) the time of each.  Synchronous. */
+int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch_ms);
+
+/* Launch shape of the step kernels: block = work-group size (a multiple of
+ * 64 in [64, 512], 0 = library default 256); order = work-group order,
+ * 1 = contiguous runs of cells per XCD (default), 2 = plain dispatch order,
+ * 0 = default.  ESBGK_EINVAL otherwise. */
+int esbgk_set_tile(esbgk_t *h, int block, int order);
+int esbgk_get_tile(const esbgk_t *h, int *block, int *order);
+
+/* Time the candidate tiles for this handle on its own state (which it then
+ * restores), keep the fastest and, if cache_path is not NULL, record it in
+ * that file keyed by lattice, storage and size class.  Synchronous. */
+int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
+
+/* Release the handle and the memory the library owns.  NULL is a no-op. */
+void esbgk_destroy(esbgk_t *h);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent periodic 2D or 3D domains of one lattice and
+ * one storage mode, each with its own size and (N_f, Pr, tau, kappa),
+ * advanced together by one persistent kernel launch per call.
+ * ---------------------------------------------------------------------- */
+
+typedef struct {
+    int N_f;
+    double Pr, tau, kappa;   /* kappa <= 0 selects the default 0.2 */
+    int64_t dims[3];         /* dims[2] ignored in 2D */
+} esbgk_domain_desc;
+
+/* Create a batch of n domains of lattice (D, Q).  The library allocates all
+ * storage in one device buffer.  Same validation per domain as
+ * esbgk_create. */
+int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int storage, esbgk_batch_t **out);
+
+int esbgk_batch_set_stream(esbgk_batch_t *b, void *hip_stream);
+
+/* Equilibrium start of domain k (fields as for esbgk_init_fields). */
+int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const double *u, const double *T);
+
+/* Advance every domain by n steps (asynchronous).  mode 0: one persistent
+ * kernel launch that loops over all n steps (per-domain step ordering is
+ * kept by device-side counters; launched through a captured HIP graph);
+ * mode 1: one launch per step covering every domain; mode 2: one launch per
+ * domain per step (the per-domain loop baseline).  All modes give bitwise
+ * identical results. */
+int esbgk_batch_step(esbgk_batch_t *b, int64_t n, int mode);
+
+int esbgk_batch_read_moments(esbgk_batch_t *b, int k, double *rho, double *u, double *T, double *P);
+int esbgk_batch_totals(esbgk_batch_t *b, int k, double *out);
+int esbgk_batch_read_populations(esbgk_batch_t *b, int k, double *f, double *g);
+
+/* Total cells over all domains, and population bytes one step moves
+ * (read + write) over all domains. */
+int esbgk_batch_info(const esbgk_batch_t *b, int64_t *cells, double *bytes_per_step);
+
+/* Persistent-kernel diagnostics of the last mode-0 call: *status 0 = ran to
+ * completion, 1 = a bounded wait timed out (the kernel then stopped early
+ * and the state is invalid). */
+int esbgk_batch_status(esbgk_batch_t *b, int *status);
+
+void esbgk_batch_destroy(esbgk_batch_t *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ESBGK_H */

@@ -1,0 +1,239 @@
+"""MI355X (gfx950) ES-BGK lattice Boltzmann stream-collide library.
+
+Thin ctypes binding of the C ABI in ``include/esbgk.h``: every call marshals
+numpy arrays and forwards to ``libesbgk.so``; all arithmetic of the scheme
+runs in the library's HIP kernels.  PyTorch supplies device memory (the
+population storage is a torch uint8 tensor) and the HIP stream.
+
+The library must have been built (``python -m paper_1611_02409_amd.build``);
+importing this package without it raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # loaded first so that the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libesbgk.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1611_02409_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_ip = ctypes.POINTER(ctypes.c_int)
+_vp = ctypes.c_void_p
+
+F32, F16_DEV, BF16_DEV = 0, 1, 2
+STORAGE = {"f32": F32, "f16": F16_DEV, "bf16": BF16_DEV}
+ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EDEVICE", -5: "ESTATE", -6: "ENONFINITE", -7: "EIO"}
+
+
+class EsbgkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _sig(name, args, res=ctypes.c_int):
+    fn = getattr(_lib, name)
+    fn.argtypes = args
+    fn.restype = res
+    return fn
+
+
+_sig("esbgk_last_error", [], ctypes.c_char_p)
+_sig("esbgk_version", [], ctypes.c_char_p)
+_sig("esbgk_lattice_info", [ctypes.c_int, ctypes.c_int, _ip, _dp, _dp, _ip])
+_sig("esbgk_params", [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp])
+_sig("esbgk_create", [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _i64p, ctypes.c_int,
+                      ctypes.POINTER(_vp)])
+_sig("esbgk_create_ex", [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _i64p,
+                         ctypes.c_int, _vp, ctypes.c_size_t, _vp, ctypes.POINTER(_vp)])
+_sig("esbgk_storage_bytes", [ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int,
+                             ctypes.POINTER(ctypes.c_size_t)])
+_sig("esbgk_set_kappa", [_vp, ctypes.c_double])
+_sig("esbgk_set_stream", [_vp, _vp])
+_sig("esbgk_init_fields", [_vp, _dp, _dp, _dp])
+_sig("esbgk_step", [_vp, ctypes.c_int64])
+_sig("esbgk_step_count", [_vp, _i64p])
+_sig("esbgk_read_moments", [_vp, _dp, _dp, _dp, _dp])
+_sig("esbgk_totals", [_vp, _dp])
+_sig("esbgk_read_cells", [_vp, ctypes.c_int64, _i64p, _dp, _dp])
+_sig("esbgk_read_populations", [_vp, _dp, _dp])
+_sig("esbgk_write_populations", [_vp, _dp, _dp])
+_sig("esbgk_save", [_vp, ctypes.c_char_p])
+_sig("esbgk_load", [_vp, ctypes.c_char_p])
+_sig("esbgk_step_timed", [_vp, ctypes.c_int64, _dp, _dp])
+_sig("esbgk_set_tile", [_vp, ctypes.c_int, ctypes.c_int])
+_sig("esbgk_get_tile", [_vp, _ip, _ip])
+_sig("esbgk_destroy", [_vp], None)
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise EsbgkError(rc, _lib.esbgk_last_error().decode())
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def version() -> str:
+    return _lib.esbgk_version().decode()
+
+
+def lattice_info(D: int, Q: int) -> dict:
+    """Velocities c (Q x D), weights w, scale r and reach of a lattice, in the
+    library's storage order."""
+    c = np.zeros(3 * Q, dtype=np.int32)
+    w = np.zeros(Q)
+    r = ctypes.c_double()
+    reach = ctypes.c_int()
+    _check(_lib.esbgk_lattice_info(D, Q, c.ctypes.data_as(_ip), _p(w), ctypes.byref(r), ctypes.byref(reach)))
+    return dict(c=c.reshape(Q, 3)[:, :D].copy(), w=w, r=r.value, reach=reach.value)
+
+
+def params(D: int, Nf: int, Pr: float, tau: float, kappa: float = 0.2) -> dict:
+    out = np.zeros(4)
+    _check(_lib.esbgk_params(D, Nf, Pr, tau, kappa, _p(out)))
+    return dict(omega=out[0], omega_s=out[1], nu=out[2], gamma=out[3])
+
+
+def _dims(dims):
+    return (ctypes.c_int64 * 3)(*(list(dims) + [1] * (3 - len(dims))))
+
+
+def storage_bytes(D, Q, Nf, dims, storage="f32") -> int:
+    out = ctypes.c_size_t()
+    _check(_lib.esbgk_storage_bytes(D, Q, Nf, _dims(dims), STORAGE[storage], ctypes.byref(out)))
+    return out.value
+
+
+class Lattice:
+    """One periodic domain.  Fields use numpy shape (ny, nx) / (nz, ny, nx),
+    velocity (D, ...)."""
+
+    def __init__(self, D: int, Q: int, Nf: int, Pr: float, tau: float, dims, storage: str = "f32",
+                 kappa: float = 0.2, device: int = 0, stream=None):
+        self.D, self.Q, self.Nf, self.Pr, self.tau = D, Q, Nf, Pr, tau
+        self.dims = tuple(int(d) for d in dims)
+        if len(self.dims) != D:
+            raise ValueError("dims must have D entries")
+        self.storage = storage
+        self.ncell = int(np.prod(self.dims))
+        self.shape = tuple(reversed(self.dims))
+        self._h = None
+        nbytes = storage_bytes(D, Q, Nf, self.dims, storage)
+        self.device = torch.device("cuda", device)
+        self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        _check(_lib.esbgk_create_ex(D, Q, Nf, Pr, tau, _dims(self.dims), STORAGE[storage], self._buf.data_ptr(),
+                                    nbytes, self._stream.cuda_stream, ctypes.byref(h)))
+        self._h = h
+        if kappa != 0.2:
+            self.set_kappa(kappa)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.esbgk_destroy(h)
+            self._h = None
+
+    @property
+    def stream(self):
+        return self._stream
+
+    @property
+    def storage_tensor(self) -> torch.Tensor:
+        return self._buf
+
+    def set_kappa(self, kappa: float):
+        _check(_lib.esbgk_set_kappa(self._h, kappa))
+
+    def set_stream(self, stream):
+        self._stream = stream
+        _check(_lib.esbgk_set_stream(self._h, stream.cuda_stream))
+
+    def init_fields(self, rho, u, T):
+        n = self.ncell
+        _check(_lib.esbgk_init_fields(self._h, _p(_f64(rho, n)), _p(_f64(u, self.D * n)), _p(_f64(T, n))))
+
+    def step(self, n: int = 1):
+        _check(_lib.esbgk_step(self._h, int(n)))
+
+    @property
+    def steps(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.esbgk_step_count(self._h, ctypes.byref(v)))
+        return v.value
+
+    def read_moments(self, with_P: bool = False) -> dict:
+        n = self.ncell
+        rho, u, T = np.zeros(n), np.zeros(self.D * n), np.zeros(n)
+        npc = self.D * (self.D + 1) // 2
+        P = np.zeros(npc * n) if with_P else None
+        _check(_lib.esbgk_read_moments(self._h, _p(rho), _p(u), _p(T), _p(P)))
+        out = dict(rho=rho.reshape(self.shape), u=u.reshape((self.D,) + self.shape), T=T.reshape(self.shape))
+        if with_P:
+            out["P"] = P.reshape((npc,) + self.shape)
+        return out
+
+    def totals(self) -> np.ndarray:
+        out = np.zeros(2 + self.D)
+        _check(_lib.esbgk_totals(self._h, _p(out)))
+        return out
+
+    def read_cells(self, cells):
+        cells = np.ascontiguousarray(cells, dtype=np.int64).reshape(-1)
+        f = np.zeros((cells.size, self.Q))
+        g = np.zeros((cells.size, self.Q)) if self.Nf > 0 else None
+        _check(_lib.esbgk_read_cells(self._h, cells.size, cells.ctypes.data_as(_i64p), _p(f), _p(g)))
+        return f, g
+
+    def read_populations(self):
+        f = np.zeros(self.Q * self.ncell)
+        g = np.zeros(self.Q * self.ncell) if self.Nf > 0 else None
+        _check(_lib.esbgk_read_populations(self._h, _p(f), _p(g)))
+        f = f.reshape((self.Q,) + self.shape)
+        return f, (g.reshape((self.Q,) + self.shape) if g is not None else None)
+
+    def write_populations(self, f, g=None):
+        n = self.Q * self.ncell
+        _check(_lib.esbgk_write_populations(self._h, _p(_f64(f, n)), _p(_f64(g, n)) if self.Nf > 0 else None))
+
+    def save(self, path: str):
+        _check(_lib.esbgk_save(self._h, os.fsencode(path)))
+
+    def load(self, path: str):
+        _check(_lib.esbgk_load(self._h, os.fsencode(path)))
+
+    def step_timed(self, n: int):
+        tot = ctypes.c_double()
+        per = np.zeros(int(n))
+        _check(_lib.esbgk_step_timed(self._h, int(n), ctypes.byref(tot), _p(per)))
+        return tot.value, per
+
+    def set_tile(self, block: int = 0, order: int = 0):
+        _check(_lib.esbgk_set_tile(self._h, block, order))
+
+    def get_tile(self):
+        b, o = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.esbgk_get_tile(self._h, ctypes.byref(b), ctypes.byref(o)))
+        return b.value, o.value

@@ -1,0 +1,610 @@
+// Device code of the ES-BGK stream-collide step for gfx950 (MI355X).
+//
+// Data layout (per population set f or g): Q planes of ncell values, plane i
+// holding direction i of the lattice's storage order, cells x-fastest.  Each
+// value is stored as a deviation from the rest state scaled by a per-shell
+// power of two s = 2^k (k = floor(log2(1/w))):
+//     F_i = s_i (f_i - w_i),     E_i = s_i (g_i - w_i N_f/2)
+// (rho0 = T0 = 1), in FP32, FP16 or BF16.  Scaling by a power of two is exact,
+// so FP32 results equal those of unscaled deviations; in FP16/BF16 it keeps
+// the small-weight directions in the normal range.
+//
+// Streaming uses the A-A pattern in place: after an even number of steps
+// f_i(x) sits at (x, plane i); after an odd number it sits at
+// (x - c_i, plane opp(i)).  The even kernel reads the own cell's planes i and
+// writes plane opp(i); the odd kernel reads (x - c, plane -c) and (x + c,
+// plane +c) and writes the same two locations with the post-collision values
+// of +c and -c.  Each thread reads and writes exactly the same set of
+// locations, so the update is race-free without a second buffer.
+//
+// The collision (Section V of the paper) per cell, in FP32 registers:
+//   moments rho, j, second moment -> u, sigma, T_tr, T_int, T_eq, T_rel;
+//   A = Lambda - delta with Lambda = (1-kappa)[(1-nu)T_tr delta + nu sigma]
+//       + kappa T_eq delta;
+//   target G_i = w_i rho (E_i +- O_i) from the general-term coefficients
+//   a^(1..4) contracted with H^(1..4)(xi_i), written through the invariants
+//   s1 = u.xi, a = xi.A.xi, b = u.A.xi, c = xi.A^2.xi, t = tr A, U = u.u,
+//   m = u.A.u, q = A:A per velocity pair +-xi (E even, O odd in xi):
+//     E - 1 = h/2 + h^2/8 - s1^4/12 - c/2 - b s1 + q/4 + m/2,  h = a - t - U + s1^2
+//     O     = s1 (1 + (a - t - U)/2 + s1^2/6) - b
+//   (the sum of a^(n).H^(n)/n! for n <= 4 of Eq. GExpansion);
+//   relax f toward G and g toward (N_f/2) T_rel G at rate omega; then restore
+//   the pre-collision mass and momentum exactly in FP32 (a projection that is
+//   identically zero in exact arithmetic and removes the drift that FP32
+//   rounding of the lattice constants would otherwise cause).
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+#include "lattice.hpp"
+
+namespace esbgk {
+
+enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+template <int S>
+struct StoreBytes {
+    static constexpr uint32_t value = S == ST_F32 ? 4u : 2u;
+};
+
+// --------------------------------------------------------------------------
+// Small helpers
+// --------------------------------------------------------------------------
+
+// n / d for n < 2^31 with a precomputed multiplier (round-up method):
+// s = ceil(log2 d), m = floor(2^32 (2^s - d)/d) + 1, q = (umulhi(n, m) + n) >> s.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) { return (__umulhi(n, f.m) + n) >> f.s; }
+
+struct Geom {
+    uint32_t nx, ny, nz, ncell;
+    FastDiv by_nx, by_nxy;
+};
+
+// Collision constants of one domain (FP32).
+struct Coll {
+    float omega;        // heat-flux (collision) rate
+    float kappa, nu;    // Lambda / T_rel blend and ES parameter
+    float r2;           // r^2 (xi = r c)
+    float hN;           // N_f / 2
+    float two_over_nf;  // 2 / N_f (0 when N_f = 0)
+    float cD, cN;       // D/(D+N_f), N_f/(D+N_f)
+    float wh[MAX_SHELL];   // s w per shell
+    float isc[MAX_SHELL];  // 1/s per shell
+};
+
+template <int C>
+__device__ __forceinline__ float acc_c(float acc, float v) {
+    if constexpr (C == 0) return acc;
+    else if constexpr (C == 1) return acc + v;
+    else if constexpr (C == -1) return acc - v;
+    else return __builtin_fmaf(float(C), v, acc);
+}
+
+template <int C>
+__device__ __forceinline__ float mul_c(float v) {
+    if constexpr (C == 1) return v;
+    else if constexpr (C == -1) return -v;
+    else return float(C) * v;
+}
+
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <class L, int P>
+constexpr bool first_in_shell() { return P == 0 || L::P[P - 1].shell != L::P[P].shell; }
+template <class L, int P>
+constexpr bool last_in_shell() { return P == L::NP - 1 || L::P[P + 1].shell != L::P[P].shell; }
+
+// --------------------------------------------------------------------------
+// Storage codecs over buffer resources.  One resource spans a whole
+// population set (all Q planes, at most 4 GiB); the plane is selected by the
+// scalar offset plane * plane_bytes, the cell by the per-lane offset.  Reads
+// past the set return 0 and stores past it are dropped.
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t set_rsrc(char *base, uint32_t set_bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)set_bytes, 0x00020000);
+}
+
+template <int S>
+__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    if constexpr (S == ST_F32) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+    } else if constexpr (S == ST_F16) {
+        unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
+        return __half2float(__ushort_as_half(h));
+    } else {
+        unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
+        return __uint_as_float(uint32_t(h) << 16);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    if constexpr (S == ST_F32) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, 0);
+    } else if constexpr (S == ST_F16) {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)off, (int)soff, 0);
+    } else {
+        __builtin_amdgcn_raw_buffer_store_b16(__bfloat16_as_ushort(__float2bfloat16(v)), r, (int)off, (int)soff, 0);
+    }
+}
+
+// The two population sets of a domain as buffer resources.
+struct Sets {
+    __amdgpu_buffer_rsrc_t f, g;
+    uint32_t pb;   // bytes per plane
+    __device__ __forceinline__ Sets(char *fb, char *gb, uint32_t plane_bytes, uint32_t set_bytes)
+        : f(set_rsrc(fb, set_bytes)), g(set_rsrc(gb ? gb : fb, set_bytes)), pb(plane_bytes) {}
+    __device__ __forceinline__ uint32_t so(int plane) const { return uint32_t(plane) * pb; }
+};
+
+// --------------------------------------------------------------------------
+// Neighbour offsets: wrapped coordinates of x + k for |k| <= REACH, as byte
+// offsets, so that the location x + c costs one or two adds.
+// --------------------------------------------------------------------------
+
+template <class L, int S>
+struct Nbr {
+    static constexpr int R = L::REACH;
+    uint32_t xo[2 * R + 1], yo[2 * R + 1], zo[L::D == 3 ? 2 * R + 1 : 1];
+    uint32_t own;
+
+    __device__ __forceinline__ void init(uint32_t cell, const Geom &g) {
+        constexpr uint32_t B = StoreBytes<S>::value;
+        uint32_t x, y, z = 0;
+        if constexpr (L::D == 2) {
+            y = fdiv(cell, g.by_nx);
+            x = cell - y * g.nx;
+        } else {
+            z = fdiv(cell, g.by_nxy);
+            uint32_t rem = cell - z * (g.nx * g.ny);
+            y = fdiv(rem, g.by_nx);
+            x = rem - y * g.nx;
+        }
+        own = cell * B;
+        static_for<2 * R + 1>([&](auto kk) {
+            constexpr int k = decltype(kk)::value - R;
+            int xv = int(x) + k, yv = int(y) + k;
+            if constexpr (k < 0) {
+                xv = xv < 0 ? xv + int(g.nx) : xv;
+                yv = yv < 0 ? yv + int(g.ny) : yv;
+            } else if constexpr (k > 0) {
+                xv = xv >= int(g.nx) ? xv - int(g.nx) : xv;
+                yv = yv >= int(g.ny) ? yv - int(g.ny) : yv;
+            }
+            xo[k + R] = uint32_t(xv) * B;
+            if constexpr (L::D == 2) {
+                yo[k + R] = uint32_t(yv) * (g.nx * B);
+            } else {
+                yo[k + R] = uint32_t(yv) * (g.nx * B);
+                int zv = int(z) + k;
+                if constexpr (k < 0) zv = zv < 0 ? zv + int(g.nz) : zv;
+                else if constexpr (k > 0) zv = zv >= int(g.nz) ? zv - int(g.nz) : zv;
+                zo[k + R] = uint32_t(zv) * (g.nx * g.ny * B);
+            }
+        });
+    }
+
+    template <int CX, int CY, int CZ>
+    __device__ __forceinline__ uint32_t at() const {
+        if constexpr (L::D == 2) return xo[CX + R] + yo[CY + R];
+        else return xo[CX + R] + yo[CY + R] + zo[CZ + R];
+    }
+};
+
+// --------------------------------------------------------------------------
+// Gather / scatter of all populations of one cell.
+// ODD = false: the cell's own slots (state after an even number of steps).
+// ODD = true : A-A odd layout (state after an odd number of steps).
+// --------------------------------------------------------------------------
+
+template <class L, int S, bool ODD, bool HAS_G>
+__device__ __forceinline__ void gather(const Sets &R, const Nbr<L, S> &nb, float *F, float *E) {
+    F[0] = ld<S>(R.f, nb.own, 0);
+    if constexpr (HAS_G) E[0] = ld<S>(R.g, nb.own, 0);
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int a = 2 * p + 1, b = 2 * p + 2;
+        if constexpr (ODD) {
+            const uint32_t op = nb.template at<cx, cy, cz>();
+            const uint32_t om = nb.template at<-cx, -cy, -cz>();
+            F[a] = ld<S>(R.f, om, R.so(b));
+            F[b] = ld<S>(R.f, op, R.so(a));
+            if constexpr (HAS_G) {
+                E[a] = ld<S>(R.g, om, R.so(b));
+                E[b] = ld<S>(R.g, op, R.so(a));
+            }
+        } else {
+            F[a] = ld<S>(R.f, nb.own, R.so(a));
+            F[b] = ld<S>(R.f, nb.own, R.so(b));
+            if constexpr (HAS_G) {
+                E[a] = ld<S>(R.g, nb.own, R.so(a));
+                E[b] = ld<S>(R.g, nb.own, R.so(b));
+            }
+        }
+    });
+}
+
+// Write post-collision populations so that the layout flips parity:
+// after an even-layout read, f*_i goes to the own cell's plane opp(i); after
+// an odd-layout read, f*_i goes to (x + c_i, plane i).
+template <class L, int S, bool ODD, bool HAS_G>
+__device__ __forceinline__ void scatter(const Sets &R, const Nbr<L, S> &nb, const float *F, const float *E) {
+    st<S>(F[0], R.f, nb.own, 0);
+    if constexpr (HAS_G) st<S>(E[0], R.g, nb.own, 0);
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int a = 2 * p + 1, b = 2 * p + 2;
+        if constexpr (ODD) {
+            const uint32_t op = nb.template at<cx, cy, cz>();
+            const uint32_t om = nb.template at<-cx, -cy, -cz>();
+            st<S>(F[a], R.f, op, R.so(a));
+            st<S>(F[b], R.f, om, R.so(b));
+            if constexpr (HAS_G) {
+                st<S>(E[a], R.g, op, R.so(a));
+                st<S>(E[b], R.g, om, R.so(b));
+            }
+        } else {
+            st<S>(F[a], R.f, nb.own, R.so(b));
+            st<S>(F[b], R.f, nb.own, R.so(a));
+            if constexpr (HAS_G) {
+                st<S>(E[a], R.g, nb.own, R.so(b));
+                st<S>(E[b], R.g, nb.own, R.so(a));
+            }
+        }
+    });
+}
+
+// --------------------------------------------------------------------------
+// Per-cell macroscopic state and the Gaussian target.
+// --------------------------------------------------------------------------
+
+template <int D>
+struct CellState {
+    float drho, rho, irho;
+    float J[3];      // lattice-unit momentum sum c d (j = r J)
+    float M[6];      // lattice-unit central second moment S - J J^T/rho (xx, xy, xz, yy, yz, zz)
+    float Ttr1, Tint1, Teq1, Trel1;   // temperatures minus one
+};
+
+// Invariants of the target: with Ah = r^2 A, uh = r^2 u/r (= r^2 J/rho in
+// lattice form), the per-direction quantities are dot products with the
+// integer velocity c.
+template <int D>
+struct TargetInv {
+    float uh[3];     // s1 = uh . c
+    float Ah[6];     // a = c . Ah . c
+    float wv[3];     // b = wv . c
+    float A2[6];     // c4 = c . A2 . c
+    float tU;        // t + U
+    float K24;       // q/4 + m/2
+};
+
+__device__ __forceinline__ int sym_idx(int a, int b) {
+    // (0,0)->0 (0,1)->1 (0,2)->2 (1,1)->3 (1,2)->4 (2,2)->5
+    return a <= b ? (a == 0 ? b : (a == 1 ? 2 + b : 5)) : (b == 0 ? a : (b == 1 ? 2 + a : 5));
+}
+
+// Target invariants from A (physical, symmetric, 6 slots) and the
+// lattice-unit velocity ut = J/rho.
+template <int D>
+__device__ __forceinline__ TargetInv<D> target_inv(const float *A, const float *ut, float r2) {
+    TargetInv<D> T;
+    float t = 0, U = 0, q = 0, m = 0;
+    float Au[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        t += A[sym_idx(a, a)];
+        U += ut[a] * ut[a];
+#pragma unroll
+        for (int b = 0; b < D; b++) Au[a] += A[sym_idx(a, b)] * ut[b];
+    }
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+        m += ut[a] * Au[a];
+        T.uh[a] = r2 * ut[a];
+        T.wv[a] = r2 * Au[a];
+    }
+#pragma unroll
+    for (int a = 0; a < D; a++)
+#pragma unroll
+        for (int b = a; b < D; b++) {
+            float s = 0;
+#pragma unroll
+            for (int k = 0; k < D; k++) s += A[sym_idx(a, k)] * A[sym_idx(k, b)];
+            T.A2[sym_idx(a, b)] = r2 * s;
+            T.Ah[sym_idx(a, b)] = r2 * A[sym_idx(a, b)];
+            q += (a == b ? 1.f : 2.f) * A[sym_idx(a, b)] * A[sym_idx(a, b)];
+        }
+    U *= r2;
+    m *= r2;
+    T.tU = t + U;
+    T.K24 = 0.25f * q + 0.5f * m;
+    return T;
+}
+
+// E - 1 and O for the velocity pair +-c (c compile-time).
+template <int D, int CX, int CY, int CZ>
+__device__ __forceinline__ void target_pair(const TargetInv<D> &T, float &Em1, float &O) {
+    float s1 = 0, a = 0, b = 0, c4 = 0;
+    s1 = acc_c<CX>(s1, T.uh[0]);
+    s1 = acc_c<CY>(s1, T.uh[1]);
+    b = acc_c<CX>(b, T.wv[0]);
+    b = acc_c<CY>(b, T.wv[1]);
+    a = acc_c<CX * CX>(a, T.Ah[0]);
+    a = acc_c<2 * CX * CY>(a, T.Ah[1]);
+    a = acc_c<CY * CY>(a, T.Ah[3]);
+    c4 = acc_c<CX * CX>(c4, T.A2[0]);
+    c4 = acc_c<2 * CX * CY>(c4, T.A2[1]);
+    c4 = acc_c<CY * CY>(c4, T.A2[3]);
+    if constexpr (D == 3) {
+        s1 = acc_c<CZ>(s1, T.uh[2]);
+        b = acc_c<CZ>(b, T.wv[2]);
+        a = acc_c<2 * CX * CZ>(a, T.Ah[2]);
+        a = acc_c<2 * CY * CZ>(a, T.Ah[4]);
+        a = acc_c<CZ * CZ>(a, T.Ah[5]);
+        c4 = acc_c<2 * CX * CZ>(c4, T.A2[2]);
+        c4 = acc_c<2 * CY * CZ>(c4, T.A2[4]);
+        c4 = acc_c<CZ * CZ>(c4, T.A2[5]);
+    }
+    const float al = a - T.tU;
+    const float s2 = s1 * s1;
+    const float h = al + s2;
+    float e = h * __builtin_fmaf(0.125f, h, 0.5f);
+    e = __builtin_fmaf(-s2 * (1.0f / 12.0f), s2, e);
+    e = __builtin_fmaf(-0.5f, c4, e);
+    e = __builtin_fmaf(-b, s1, e);
+    Em1 = e + T.K24;
+    const float k = __builtin_fmaf(s2, 1.0f / 6.0f, __builtin_fmaf(0.5f, al, 1.0f));
+    O = __builtin_fmaf(s1, k, -b);
+}
+
+// Rest-direction E - 1 (c = 0).
+template <int D>
+__device__ __forceinline__ float target_rest(const TargetInv<D> &T) {
+    const float h = -T.tU;
+    return h * __builtin_fmaf(0.125f, h, 0.5f) + T.K24;
+}
+
+// --------------------------------------------------------------------------
+// Moments of one cell (scaled deviations in F, E).
+// --------------------------------------------------------------------------
+
+template <class L, bool HAS_G>
+__device__ __forceinline__ CellState<L::D> cell_moments(const Coll &cp, const float *F, const float *E) {
+    constexpr int D = L::D;
+    CellState<D> cs;
+    float drho = F[0] * cp.isc[0];
+    float J[3] = {0, 0, 0}, S[6] = {0, 0, 0, 0, 0, 0};
+    float sg = HAS_G ? E[0] * cp.isc[0] : 0.f;
+    float m0 = 0, j0 = 0, j1 = 0, j2 = 0, s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, g0 = 0;
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int sh = L::P[p].shell;
+        if constexpr (first_in_shell<L, p>()) {
+            m0 = j0 = j1 = j2 = s0 = s1 = s2 = s3 = s4 = s5 = g0 = 0;
+        }
+        const float fa = F[2 * p + 1], fb = F[2 * p + 2];
+        const float sp = fa + fb, dp = fa - fb;
+        m0 += sp;
+        j0 = acc_c<cx>(j0, dp);
+        j1 = acc_c<cy>(j1, dp);
+        s0 = acc_c<cx * cx>(s0, sp);
+        s1 = acc_c<cx * cy>(s1, sp);
+        s3 = acc_c<cy * cy>(s3, sp);
+        if constexpr (D == 3) {
+            j2 = acc_c<cz>(j2, dp);
+            s2 = acc_c<cx * cz>(s2, sp);
+            s4 = acc_c<cy * cz>(s4, sp);
+            s5 = acc_c<cz * cz>(s5, sp);
+        }
+        if constexpr (HAS_G) g0 += E[2 * p + 1] + E[2 * p + 2];
+        if constexpr (last_in_shell<L, p>()) {
+            const float is = cp.isc[sh];
+            drho = __builtin_fmaf(m0, is, drho);
+            J[0] = __builtin_fmaf(j0, is, J[0]);
+            J[1] = __builtin_fmaf(j1, is, J[1]);
+            S[0] = __builtin_fmaf(s0, is, S[0]);
+            S[1] = __builtin_fmaf(s1, is, S[1]);
+            S[3] = __builtin_fmaf(s3, is, S[3]);
+            if constexpr (D == 3) {
+                J[2] = __builtin_fmaf(j2, is, J[2]);
+                S[2] = __builtin_fmaf(s2, is, S[2]);
+                S[4] = __builtin_fmaf(s4, is, S[4]);
+                S[5] = __builtin_fmaf(s5, is, S[5]);
+            }
+            if constexpr (HAS_G) sg = __builtin_fmaf(g0, is, sg);
+        }
+    });
+    cs.drho = drho;
+    cs.rho = 1.0f + drho;
+    cs.irho = 1.0f / cs.rho;
+    float ut[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        cs.J[a] = a < D ? J[a] : 0.f;
+        ut[a] = cs.J[a] * cs.irho;
+    }
+    float trM = 0;
+#pragma unroll
+    for (int a = 0; a < D; a++)
+#pragma unroll
+        for (int b = a; b < D; b++) {
+            const int k = sym_idx(a, b);
+            cs.M[k] = __builtin_fmaf(-cs.J[a], ut[b], S[k]);
+            if (a == b) trM += cs.M[k];
+        }
+    // T_tr - 1 = (r^2 tr M - D drho) / (D rho)
+    cs.Ttr1 = __builtin_fmaf(cp.r2, trM, -float(D) * drho) * cs.irho * (1.0f / float(D));
+    if constexpr (HAS_G) {
+        cs.Tint1 = __builtin_fmaf(cp.two_over_nf, sg, -drho) * cs.irho;
+    } else {
+        cs.Tint1 = cs.Ttr1;
+    }
+    cs.Teq1 = __builtin_fmaf(cp.cD, cs.Ttr1, cp.cN * cs.Tint1);
+    cs.Trel1 = __builtin_fmaf(cp.kappa, cs.Teq1, (1.0f - cp.kappa) * cs.Tint1);
+    return cs;
+}
+
+// A = Lambda - delta from the cell state.
+template <int D>
+__device__ __forceinline__ void lambda_minus_delta(const Coll &cp, const CellState<D> &cs, float *A) {
+    const float omk = 1.0f - cp.kappa;
+    const float beta = omk * cp.nu * cp.r2 * cs.irho;
+    const float alpha = omk * (1.0f - cp.nu) * cs.Ttr1 + cp.kappa * cs.Teq1 - omk * cp.nu * cs.drho * cs.irho;
+#pragma unroll
+    for (int k = 0; k < 6; k++) A[k] = beta * cs.M[k];
+    A[0] += alpha;
+    A[3] += alpha;
+    if constexpr (D == 3) A[5] += alpha;
+}
+
+// --------------------------------------------------------------------------
+// The collision of one cell: F, E in/out (scaled deviations).
+// --------------------------------------------------------------------------
+
+template <class L, bool HAS_G>
+__device__ __forceinline__ void collide(const Coll &cp, float *F, float *E) {
+    constexpr int D = L::D;
+    const CellState<D> cs = cell_moments<L, HAS_G>(cp, F, E);
+    float A[6];
+    lambda_minus_delta<D>(cp, cs, A);
+    float ut[3] = {cs.J[0] * cs.irho, cs.J[1] * cs.irho, cs.J[2] * cs.irho};
+    const TargetInv<D> T = target_inv<D>(A, ut, cp.r2);
+
+    const float om = cp.omega;
+    const float rho = cs.rho, drho = cs.drho;
+    const float gT = cp.hN * (1.0f + cs.Trel1);  // (N_f/2) T_rel
+    const float gT1 = cp.hN * cs.Trel1;          // (N_f/2)(T_rel - 1)
+
+    // rest direction
+    {
+        const float X = cp.wh[0] * __builtin_fmaf(rho, target_rest<D>(T), drho);
+        F[0] = __builtin_fmaf(om, X - F[0], F[0]);
+        if constexpr (HAS_G) {
+            const float gt = __builtin_fmaf(gT, X, gT1 * cp.wh[0]);
+            E[0] = __builtin_fmaf(om, gt - E[0], E[0]);
+        }
+    }
+    // velocity pairs: relax, and accumulate the post-collision mass and
+    // momentum of f per shell for the projection
+    float pm = F[0] * cp.isc[0], pJ[3] = {0, 0, 0};
+    float m0 = 0, j0 = 0, j1 = 0, j2 = 0;
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int sh = L::P[p].shell;
+        constexpr int a = 2 * p + 1, b = 2 * p + 2;
+        if constexpr (first_in_shell<L, p>()) m0 = j0 = j1 = j2 = 0;
+        float Em1, O;
+        target_pair<D, cx, cy, cz>(T, Em1, O);
+        const float w = cp.wh[sh];
+        const float X = w * __builtin_fmaf(rho, Em1, drho);
+        const float Y = (w * rho) * O;
+        const float Ga = X + Y, Gb = X - Y;
+        const float fa = __builtin_fmaf(om, Ga - F[a], F[a]);
+        const float fb = __builtin_fmaf(om, Gb - F[b], F[b]);
+        F[a] = fa;
+        F[b] = fb;
+        if constexpr (HAS_G) {
+            const float c0 = gT1 * w;
+            const float ga = __builtin_fmaf(gT, Ga, c0), gb = __builtin_fmaf(gT, Gb, c0);
+            E[a] = __builtin_fmaf(om, ga - E[a], E[a]);
+            E[b] = __builtin_fmaf(om, gb - E[b], E[b]);
+        }
+        const float sp = fa + fb, dp = fa - fb;
+        m0 += sp;
+        j0 = acc_c<cx>(j0, dp);
+        j1 = acc_c<cy>(j1, dp);
+        if constexpr (D == 3) j2 = acc_c<cz>(j2, dp);
+        if constexpr (last_in_shell<L, p>()) {
+            const float is = cp.isc[sh];
+            pm = __builtin_fmaf(m0, is, pm);
+            pJ[0] = __builtin_fmaf(j0, is, pJ[0]);
+            pJ[1] = __builtin_fmaf(j1, is, pJ[1]);
+            if constexpr (D == 3) pJ[2] = __builtin_fmaf(j2, is, pJ[2]);
+        }
+    });
+    // projection: f_i += w_i (dM + xi_i . dj), scaled: F_i += wh_i (dM + r^2 c_i . dJ)
+    const float dM = drho - pm;
+    const float dJ0 = cp.r2 * (cs.J[0] - pJ[0]);
+    const float dJ1 = cp.r2 * (cs.J[1] - pJ[1]);
+    const float dJ2 = D == 3 ? cp.r2 * (cs.J[2] - pJ[2]) : 0.f;
+    F[0] = __builtin_fmaf(cp.wh[0], dM, F[0]);
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int sh = L::P[p].shell;
+        float cj = 0;
+        cj = acc_c<cx>(cj, dJ0);
+        cj = acc_c<cy>(cj, dJ1);
+        if constexpr (D == 3) cj = acc_c<cz>(cj, dJ2);
+        const float w = cp.wh[sh];
+        F[2 * p + 1] = __builtin_fmaf(w, dM + cj, F[2 * p + 1]);
+        F[2 * p + 2] = __builtin_fmaf(w, dM - cj, F[2 * p + 2]);
+    });
+}
+
+// Equilibrium populations of (drho, u (physical), dT): f = G(rho, u, T delta),
+// g = (N_f/2) T G, as scaled deviations.
+template <class L, bool HAS_G>
+__device__ __forceinline__ void equilibrium(const Coll &cp, float drho, const float *u_phys, float dT, float *F,
+                                            float *E) {
+    constexpr int D = L::D;
+    const float rho = 1.0f + drho;
+    float A[6] = {0, 0, 0, 0, 0, 0};
+    A[0] = dT;
+    A[3] = dT;
+    if constexpr (D == 3) A[5] = dT;
+    // u = r ut  ->  ut = u / r;  r^2 ut = r u
+    const float r = __builtin_sqrtf(cp.r2);
+    float ut[3] = {u_phys[0] / r, u_phys[1] / r, D == 3 ? u_phys[2] / r : 0.f};
+    const TargetInv<D> T = target_inv<D>(A, ut, cp.r2);
+    const float gT = cp.hN * (1.0f + dT), gT1 = cp.hN * dT;
+    const float X0 = cp.wh[0] * __builtin_fmaf(rho, target_rest<D>(T), drho);
+    F[0] = X0;
+    if constexpr (HAS_G) E[0] = __builtin_fmaf(gT, X0, gT1 * cp.wh[0]);
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        float Em1, O;
+        target_pair<D, cx, cy, cz>(T, Em1, O);
+        const float w = cp.wh[L::P[p].shell];
+        const float X = w * __builtin_fmaf(rho, Em1, drho), Y = (w * rho) * O;
+        F[2 * p + 1] = X + Y;
+        F[2 * p + 2] = X - Y;
+        if constexpr (HAS_G) {
+            E[2 * p + 1] = __builtin_fmaf(gT, X + Y, gT1 * w);
+            E[2 * p + 2] = __builtin_fmaf(gT, X - Y, gT1 * w);
+        }
+    });
+}
+
+// XCD-aware block order: the eight XCDs take blocks round-robin; give XCD k a
+// contiguous run of logical blocks so that neighbouring tiles share its L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+    const uint32_t per = nb >> 3, rem = nb & 7u, xcd = b & 7u, loc = b >> 3;
+    return (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
+}
+
+}  // namespace esbgk

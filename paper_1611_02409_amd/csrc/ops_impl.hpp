@@ -1,0 +1,243 @@
+// Kernel entry points of the single-domain path and their launchers for one
+// (lattice, storage) combination.  Included by one translation unit per
+// lattice.
+#pragma once
+
+#include "runtime.hpp"
+
+namespace esbgk {
+
+// ---------------------------------------------------------------- step
+template <class L, int S, bool ODD, bool HAS_G>
+__global__ __launch_bounds__(512) void k_step(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
+                                              uint32_t remap) {
+    const uint32_t blk = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+    const uint32_t cell = blk * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    Nbr<L, S> nb;
+    if constexpr (ODD) nb.init(cell, g);
+    else nb.own = cell * StoreBytes<S>::value;
+    const Sets R(fb, gb, pb, sb);
+    float F[L::Q], E[HAS_G ? L::Q : 1];
+    gather<L, S, ODD, HAS_G>(R, nb, F, E);
+    collide<L, HAS_G>(cp, F, E);
+    scatter<L, S, ODD, HAS_G>(R, nb, F, E);
+}
+
+// ---------------------------------------------------------------- init
+// fields: [rho - 1 | u_x | u_y (| u_z) | T - 1], ncell floats each.
+template <class L, int S, bool HAS_G>
+__global__ __launch_bounds__(256) void k_init(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, Coll cp,
+                                              const float *fields) {
+    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= ncell) return;
+    constexpr int D = L::D;
+    float u[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; a++) u[a] = fields[(1 + a) * (uint64_t)ncell + cell];
+    float F[L::Q], E[HAS_G ? L::Q : 1];
+    equilibrium<L, HAS_G>(cp, fields[cell], u, fields[(1 + D) * (uint64_t)ncell + cell], F, E);
+    const Sets R(fb, gb, pb, sb);
+    const uint32_t own = cell * StoreBytes<S>::value;
+    // natural layout (step 0)
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        st<S>(F[i], R.f, own, R.so(i));
+        if constexpr (HAS_G) st<S>(E[i], R.g, own, R.so(i));
+    }
+}
+
+// ---------------------------------------------------------------- moments
+// out: [rho - 1 | u (D) | T_eq - 1 | P - delta (D(D+1)/2, if with_P)]
+template <class L, int S, bool ODD, bool HAS_G>
+__global__ __launch_bounds__(256) void k_moments(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
+                                                 float *out, int with_P) {
+    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    constexpr int D = L::D;
+    Nbr<L, S> nb;
+    nb.init(cell, g);
+    const Sets R(fb, gb, pb, sb);
+    float F[L::Q], E[HAS_G ? L::Q : 1];
+    gather<L, S, ODD, HAS_G>(R, nb, F, E);
+    const CellState<D> cs = cell_moments<L, HAS_G>(cp, F, E);
+    const uint64_t n = g.ncell;
+    const float r = __builtin_sqrtf(cp.r2);
+    out[cell] = cs.drho;
+#pragma unroll
+    for (int a = 0; a < D; a++) out[(1 + a) * n + cell] = r * cs.J[a] * cs.irho;
+    out[(1 + D) * n + cell] = cs.Teq1;
+    if (with_P) {
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < D; a++)
+#pragma unroll
+            for (int b = a; b < D; b++) {
+                // central pressure tensor rho sigma = r^2 M + delta (rho - drho = 1)
+                out[(2 + D + q) * n + cell] = cp.r2 * cs.M[sym_idx(a, b)];
+                q++;
+            }
+    }
+}
+
+// ---------------------------------------------------------------- read cells
+// out[k*Q + i] = f_i - w_i of listed cell k (unscaled, FP32); g after the f
+// block at offset n*Q.  list == nullptr: all cells, output as planes
+// out[i*ncell + k].
+template <class L, int S, bool ODD, bool HAS_G>
+__global__ __launch_bounds__(256) void k_cells(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
+                                               const uint32_t *list, uint32_t n, float *out) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t cell = list ? list[k] : k;
+    if (cell >= g.ncell) return;
+    Nbr<L, S> nb;
+    nb.init(cell, g);
+    const Sets R(fb, gb, pb, sb);
+    float F[L::Q], E[HAS_G ? L::Q : 1];
+    gather<L, S, ODD, HAS_G>(R, nb, F, E);
+    int sh[L::Q];
+    sh[0] = 0;
+#pragma unroll
+    for (int p = 0; p < L::NP; p++) sh[2 * p + 1] = sh[2 * p + 2] = L::P[p].shell;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const float is = cp.isc[sh[i]];
+        if (list) {
+            out[(uint64_t)k * L::Q + i] = F[i] * is;
+            if constexpr (HAS_G) out[(uint64_t)n * L::Q + (uint64_t)k * L::Q + i] = E[i] * is;
+        } else {
+            out[(uint64_t)i * n + k] = F[i] * is;
+            if constexpr (HAS_G) out[(uint64_t)(L::Q + i) * n + k] = E[i] * is;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- write populations
+// in: scaled deviations as planes in natural order ([f planes | g planes]).
+template <class L, int S, bool ODD, bool HAS_G>
+__global__ __launch_bounds__(256) void k_write(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g,
+                                               const float *in) {
+    const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.ncell) return;
+    Nbr<L, S> nb;
+    nb.init(cell, g);
+    const uint64_t n = g.ncell;
+    const Sets R(fb, gb, pb, sb);
+    st<S>(in[cell], R.f, nb.own, 0);
+    if constexpr (HAS_G) st<S>(in[L::Q * n + cell], R.g, nb.own, 0);
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int a = 2 * p + 1, b = 2 * p + 2;
+        // value of direction a at this cell lives at (x - c, plane b) in the odd layout
+        const uint32_t la = ODD ? nb.template at<-cx, -cy, -cz>() : nb.own;
+        const uint32_t lb = ODD ? nb.template at<cx, cy, cz>() : nb.own;
+        st<S>(in[a * n + cell], R.f, la, R.so(ODD ? b : a));
+        st<S>(in[b * n + cell], R.f, lb, R.so(ODD ? a : b));
+        if constexpr (HAS_G) {
+            st<S>(in[(L::Q + a) * n + cell], R.g, la, R.so(ODD ? b : a));
+            st<S>(in[(L::Q + b) * n + cell], R.g, lb, R.so(ODD ? a : b));
+        }
+    });
+}
+
+// ---------------------------------------------------------------- plane sums (FP64)
+// partials[plane * nchunks + chunk] = sum over the chunk's cells of the stored
+// value of that plane (raw scaled value, in double).
+template <int S>
+__global__ __launch_bounds__(256) void k_plane_sums(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell,
+                                                    int q, double *partials) {
+    const uint32_t chunk = blockIdx.x, nchunks = gridDim.x;
+    const int plane = blockIdx.y;
+    const auto r = set_rsrc(plane < q ? fb : gb, sb);
+    const uint32_t so = uint32_t(plane < q ? plane : plane - q) * pb;
+    const uint32_t per = (ncell + nchunks - 1) / nchunks;
+    const uint32_t lo = chunk * per, hi = min(ncell, lo + per);
+    double s = 0;
+    for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) s += (double)ld<S>(r, c * StoreBytes<S>::value, so);
+    __shared__ double red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[(uint64_t)plane * nchunks + chunk] = red[0];
+}
+
+// ---------------------------------------------------------------- launchers
+inline uint32_t nblocks(uint64_t n, int block) { return (uint32_t)((n + block - 1) / block); }
+
+template <class L, int S>
+struct OpsImpl {
+    static void step(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, int block,
+                     int remap, hipStream_t s) {
+        const uint32_t nb = nblocks(g.ncell, block);
+        if (odd) {
+            if (has_g) k_step<L, S, true, true><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            else k_step<L, S, true, false><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+        } else {
+            if (has_g) k_step<L, S, false, true><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            else k_step<L, S, false, false><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+        }
+    }
+    static void init(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
+                     hipStream_t s) {
+        const uint32_t nb = nblocks(ncell, 256);
+        if (has_g) k_init<L, S, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, ncell, c, fields);
+        else k_init<L, S, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, ncell, c, fields);
+    }
+    static void moments(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
+                        float *out, bool with_P, hipStream_t s) {
+        const uint32_t nb = nblocks(g.ncell, 256);
+        const int wp = with_P ? 1 : 0;
+        if (odd) {
+            if (has_g) k_moments<L, S, true, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
+            else k_moments<L, S, true, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
+        } else {
+            if (has_g) k_moments<L, S, false, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
+            else k_moments<L, S, false, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
+        }
+    }
+    static void cells(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
+                      const uint32_t *list, uint32_t n, float *out, hipStream_t s) {
+        const uint32_t nb = nblocks(n, 256);
+        if (odd) {
+            if (has_g) k_cells<L, S, true, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
+            else k_cells<L, S, true, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
+        } else {
+            if (has_g) k_cells<L, S, false, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
+            else k_cells<L, S, false, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
+        }
+    }
+    static void write(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, bool odd, bool has_g, const float *in,
+                      hipStream_t s) {
+        const uint32_t nb = nblocks(g.ncell, 256);
+        if (odd) {
+            if (has_g) k_write<L, S, true, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
+            else k_write<L, S, true, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
+        } else {
+            if (has_g) k_write<L, S, false, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
+            else k_write<L, S, false, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
+        }
+    }
+    static void plane_sums(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, int q, bool has_g, double *partials,
+                           uint32_t nchunks, hipStream_t s) {
+        dim3 grid(nchunks, has_g ? 2 * q : q);
+        k_plane_sums<S><<<grid, 256, 0, s>>>(fb, gb, pb, sb, ncell, q, partials);
+    }
+    static constexpr Ops ops{&step, &init, &moments, &cells, &write, &plane_sums};
+};
+
+}  // namespace esbgk
+
+#define ESBGK_INSTANTIATE_LATTICE(LAT, NAME)                                               \
+    namespace esbgk {                                                                      \
+    const Ops *ops_##NAME(int storage) {                                                   \
+        static constexpr Ops o32 = OpsImpl<LAT, ST_F32>::ops;                              \
+        static constexpr Ops o16 = OpsImpl<LAT, ST_F16>::ops;                              \
+        static constexpr Ops ob16 = OpsImpl<LAT, ST_BF16>::ops;                            \
+        return storage == ST_F32 ? &o32 : storage == ST_F16 ? &o16 : &ob16;                \
+    }                                                                                      \
+    }

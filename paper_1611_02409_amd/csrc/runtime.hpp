@@ -1,0 +1,76 @@
+// Host-side runtime shared by the single-domain and batched entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/esbgk.h"
+#include "kernels.hpp"
+#include "lattice.hpp"
+
+namespace esbgk {
+
+// Thread-local error message and status helpers.
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define ESBGK_HIP(call)                                                                                  \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) {                                                                          \
+            ::esbgk::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return e_ == hipErrorOutOfMemory ? ESBGK_ENOMEM : ESBGK_EDEVICE;                             \
+        }                                                                                                \
+    } while (0)
+
+FastDiv make_fastdiv(uint32_t d);
+
+// Validate (D, Q, N_f, Pr, tau, kappa, dims, storage) and fill the derived
+// constants.  Returns ESBGK_OK or an error code with the message set.
+struct DomainSetup {
+    LatticeConsts lc;
+    double prm[4];  // omega, omega_s, nu, gamma
+    Coll coll;
+    Geom geom;
+    int npop;
+    uint32_t esize;
+    uint64_t plane_bytes, bytes;
+};
+
+int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, const int64_t *dims, int storage,
+                 DomainSetup &out);
+
+// Collision constants for the given parameters.
+Coll make_coll(const LatticeConsts &lc, const double prm[4], int D, int Nf, double kappa);
+
+// Host-side field conversion to the FP32 deviations the init kernel reads:
+// out = [rho - 1 | u (D planes) | T - 1], each ncell floats.
+int fields_to_dev(const double *rho, const double *u, const double *T, int D, uint64_t ncell, float *out);
+
+// Kernel dispatch of one (lattice, storage) combination.
+struct Ops {
+    void (*step)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, int block,
+                 int remap, hipStream_t s);
+    void (*init)(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
+                 hipStream_t s);
+    void (*moments)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, float *out,
+                    bool with_P, hipStream_t s);
+    void (*cells)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
+                  const uint32_t *list, uint32_t n, float *out, hipStream_t s);
+    void (*write)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, bool odd, bool has_g, const float *in,
+                  hipStream_t s);
+    void (*plane_sums)(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, int nplanes_per_set, bool has_g,
+                       double *partials, uint32_t nchunks, hipStream_t s);
+};
+
+const Ops *get_ops(int D, int Q, int storage);
+
+// Final FP64 reduction of plane sums into totals (one block on the GPU).
+void launch_totals_final(const double *partials, uint32_t nchunks, const LatticeConsts &lc, int npop, bool odd,
+                         uint64_t ncell, double hN, double *out, hipStream_t s);
+
+}  // namespace esbgk

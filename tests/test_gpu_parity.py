@@ -1,0 +1,217 @@
+"""GPU parity of the HIP stream-collide path against the FP64 oracle.
+
+Every test drives the library through its C ABI (the ctypes binding) on the
+seeded inputs of ``workloads.py`` and compares with the oracle element by
+element.  Tolerances (FP32 storage): populations within 3e-6 w_i after a
+few steps of strongly perturbed states (FP32 has 6e-8 relative rounding; the
+collision chains ~50 dependent operations on values up to O(1) times w_i),
+moments within the 1e-5 relative bound of the FP32 target.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+from gpu_helpers import neighbourhood, oracle_run, pert_l2, pop_error, rel_l2  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+esb = pytest.importorskip("paper_1611_02409_amd")
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def perm_to_oracle(D, Q):
+    li = esb.lattice_info(D, Q)
+    L = oracle.Lattice(D, Q)
+    oc = [tuple(x) for x in L.c]
+    return np.array([oc.index(tuple(c)) for c in li["c"]]), li
+
+
+def gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, storage="f32", kappa=0.2):
+    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, kappa=kappa)
+    lat.init_fields(*fields)
+    if steps:
+        lat.step(steps)
+    return lat
+
+
+CASES = [
+    # D, Q, Nf, Pr, tau, dims
+    (2, 37, 3, 0.71, 0.6, (64, 48)),
+    (2, 37, 0, 2.0, 0.9, (40, 36)),
+    (2, 37, 1, 0.5, 1.2, (33, 35)),
+    (3, 39, 2, 0.71, 0.7, (12, 10, 8)),
+    (2, 33, 3, 0.71, 2 / 3, (40, 24)),
+]
+
+
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,dims", CASES)
+def test_init_matches_oracle(D, Q, Nf, Pr, tau, dims):
+    fields = workloads.random_state(dims, seed=11)
+    perm, li = perm_to_oracle(D, Q)
+    lat = gpu_run(D, Q, Nf, Pr, tau, dims, fields, 0)
+    sim = oracle_run(D, Q, Nf, Pr, tau, dims, fields, 0)
+    fg, gg = lat.read_populations()
+    fo, go = sim.get_pops()
+    e = pop_error(li["w"], fg, fo[perm])
+    print(f"init D{D}Q{Q} Nf={Nf}: pop err {e:.3e}")
+    assert e < 1e-6
+    if Nf:
+        assert pop_error(li["w"], gg, go[perm]) < 1e-6 * max(1, Nf)
+    m = lat.read_moments()
+    assert rel_l2(m["rho"], fields[0]) < 1e-7
+    assert rel_l2(m["T"], fields[2]) < 1e-7
+    assert rel_l2(m["u"], fields[1]) < 1e-6
+
+
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,dims", CASES)
+@pytest.mark.parametrize("steps", [1, 2, 3, 10])
+def test_step_matches_oracle(D, Q, Nf, Pr, tau, dims, steps):
+    """Populations after 1, 2, 3 and 10 steps (both A-A parities) on a
+    strongly perturbed state with ragged, non-square grids."""
+    fields = workloads.random_state(dims, seed=12)
+    perm, li = perm_to_oracle(D, Q)
+    lat = gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps)
+    sim = oracle_run(D, Q, Nf, Pr, tau, dims, fields, steps)
+    fg, gg = lat.read_populations()
+    fo, go = sim.get_pops()
+    e = pop_error(li["w"], fg, fo[perm])
+    eg = pop_error(li["w"], gg, go[perm]) / max(1, Nf) if Nf else 0.0
+    mg, mo = lat.read_moments(), sim.moments()
+    er, eu, eT = rel_l2(mg["rho"], mo["rho"]), rel_l2(mg["u"], mo["u"]), rel_l2(mg["T"], mo["T"])
+    print(f"D{D}Q{Q} Nf={Nf} steps={steps}: pop {e:.2e} g {eg:.2e} rho {er:.2e} u {eu:.2e} T {eT:.2e}")
+    assert e < 3e-6 and eg < 3e-6
+    assert er < 1e-6 and eu < 1e-5 and eT < 1e-6
+
+
+def test_split_steps_bitwise():
+    dims = (48, 40)
+    fields = workloads.random_state(dims, seed=13)
+    a = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 0)
+    a.step(3)
+    a.step(4)
+    b = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 7)
+    fa, ga = a.read_populations()
+    fb, gb = b.read_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    assert a.steps == b.steps == 7
+
+
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,dims", CASES)
+def test_totals_match_oracle_and_are_conserved(D, Q, Nf, Pr, tau, dims):
+    fields = workloads.random_state(dims, seed=14)
+    lat = gpu_run(D, Q, Nf, Pr, tau, dims, fields, 0)
+    t0 = lat.totals()
+    lat.step(25)
+    t1 = lat.totals()
+    sim = oracle_run(D, Q, Nf, Pr, tau, dims, fields, 25)
+    to = sim.totals()
+    n = np.prod(dims)
+    print(f"totals D{D}Q{Q}: gpu {t1} oracle {to} drift {t1 - t0}")
+    # mass and energy per cell to FP32 rounding of the stored deviations
+    assert abs(t1[0] - to[0]) / n < 1e-7
+    assert abs(t1[-1] - to[-1]) / n < 1e-6
+    assert np.all(np.abs(t1[1:-1] - to[1:-1]) / n < 1e-7)
+    assert abs(t1[0] - t0[0]) / n < 1e-7
+
+
+@pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 1.6e-2)])
+def test_reduced_storage_one_step(storage, tol):
+    """FP16 / BF16 storage of scaled deviations: after init and after one
+    step the stored values differ from the oracle by the storage rounding of
+    a deviation of this size (relative 2^-11 for FP16, 2^-8 for BF16, of
+    values up to ~0.5 w_i, plus the FP32 collision)."""
+    D, Q, Nf, Pr, tau, dims = 2, 37, 3, 0.71, 0.6, (40, 32)
+    fields = workloads.random_state(dims, seed=15)
+    perm, li = perm_to_oracle(D, Q)
+    for steps in (0, 1, 2):
+        lat = gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, storage=storage)
+        sim = oracle_run(D, Q, Nf, Pr, tau, dims, fields, steps)
+        fg, _ = lat.read_populations()
+        fo, _ = sim.get_pops()
+        e = pop_error(li["w"], fg, fo[perm])
+        print(f"{storage} steps={steps}: pop err {e:.3e}")
+        assert e < tol
+
+
+def test_decay_case_moments_match_oracle():
+    """Plain-method decay case (32^2, 500 steps): rho, u, T within 1e-5."""
+    n = 32
+    fields = workloads.decay_2d(n)
+    lat = gpu_run(2, 37, 3, 0.71, 0.8, (n, n), fields, 500)
+    sim = oracle_run(2, 37, 3, 0.71, 0.8, (n, n), fields, 500)
+    mg, mo = lat.read_moments(), sim.moments()
+    er, eu, eT = rel_l2(mg["rho"], mo["rho"]), rel_l2(mg["u"], mo["u"]), rel_l2(mg["T"], mo["T"])
+    print(f"decay 32^2 x 500: rho {er:.2e} u {eu:.2e} T {eT:.2e}  pert T {pert_l2(mg['T'], mo['T']):.2e}")
+    assert er < 1e-5 and eu < 1e-5 and eT < 1e-5
+
+
+@pytest.mark.parametrize("steps0", [2, 3])
+def test_full_size_one_step_sampled(steps0):
+    """4096^2 FP32 (the benchmark configuration): after steps0 steps, one more
+    step of the GPU at 64 sampled cells equals the oracle's collision of the
+    GPU's own pre-step populations at the neighbours x - c_i, streamed."""
+    N = 4096
+    D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
+    fields = workloads.waves_noise_2d(N)
+    perm, li = perm_to_oracle(D, Q)
+    lat = gpu_run(D, Q, Nf, Pr, tau, (N, N), fields, steps0)
+    rng = np.random.default_rng(steps0)
+    cells = np.concatenate([rng.integers(0, N * N, 60), [0, N - 1, N * N - 1, N * (N - 1)]])
+    nb = neighbourhood((N, N), cells, li["c"])
+    f0, g0 = lat.read_cells(nb.ravel())
+    lat.step(1)
+    f1, g1 = lat.read_cells(cells)
+    # oracle collision of the neighbour cells, in oracle direction order
+    inv = np.argsort(perm)        # oracle index -> library index
+    fo, go = oracle.collide_cells(D, Q, Nf, Pr, tau, 0.2, f0[:, inv], g0[:, inv])
+    fo, go = fo[:, perm], go[:, perm]     # back to library order
+    fo = fo.reshape(cells.size, Q, Q)
+    go = go.reshape(cells.size, Q, Q)
+    # direction i of sample k comes from neighbour (k, i)
+    want_f = fo[np.arange(cells.size)[:, None], np.arange(Q)[None, :], np.arange(Q)[None, :]]
+    want_g = go[np.arange(cells.size)[:, None], np.arange(Q)[None, :], np.arange(Q)[None, :]]
+    ef = float(np.max(np.abs(f1 - want_f) / li["w"]))
+    eg = float(np.max(np.abs(g1 - want_g) / li["w"])) / Nf
+    print(f"4096^2 sampled step {steps0}->{steps0 + 1}: f {ef:.2e} g {eg:.2e}")
+    assert ef < 1e-6 and eg < 1e-6
+
+
+def test_save_load_continues_bitwise(tmp_path):
+    dims = (32, 32)
+    fields = workloads.random_state(dims, seed=16)
+    a = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 10)
+    b = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 5)
+    p = str(tmp_path / "ck.bin")
+    b.save(p)
+    c = esb.Lattice(2, 37, 3, 0.71, 0.6, dims)
+    c.load(p)
+    assert c.steps == 5
+    c.step(5)
+    fa, ga = a.read_populations()
+    fc, gc = c.read_populations()
+    assert np.array_equal(fa, fc) and np.array_equal(ga, gc)
+
+
+def test_write_populations_roundtrip():
+    D, Q, Nf, dims = 2, 37, 3, (24, 20)
+    fields = workloads.random_state(dims, seed=17)
+    sim = oracle_run(D, Q, Nf, 0.71, 0.6, dims, fields, 3)
+    perm, li = perm_to_oracle(D, Q)
+    fo, go = sim.get_pops()
+    lat = gpu_run(D, Q, Nf, 0.71, 0.6, dims, fields, 3)      # odd layout
+    lat.write_populations(fo[perm], go[perm])
+    fg, gg = lat.read_populations()
+    assert pop_error(li["w"], fg, fo[perm]) < 1e-7
+    lat.step(2)
+    sim.step(2)
+    fg, _ = lat.read_populations()
+    fo2, _ = sim.get_pops()
+    assert pop_error(li["w"], fg, fo2[perm]) < 3e-6
