@@ -172,15 +172,21 @@ int esbgk_load(esbgk_t *h, const char *path);
 int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch_ms);
 
 /* Launch shape of the step kernels: block = work-group size (a multiple of
- * 64 in [64, 512], 0 = library default 256); order = work-group order,
- * 1 = contiguous runs of cells per XCD (default), 2 = plain dispatch order,
- * 0 = default.  ESBGK_EINVAL otherwise. */
-int esbgk_set_tile(esbgk_t *h, int block, int order);
-int esbgk_get_tile(const esbgk_t *h, int *block, int *order);
+ * 64 in [64, 512]; 0 = default 256); order = work-group order over the
+ * cells (0 = default = 1; 1 = dispatch order; 2 = contiguous runs of cells
+ * per XCD); policy = cache policy of the population loads and stores
+ * (0 = default = 1; 1 = normal; 2 = non-temporal).  ESBGK_EINVAL otherwise.
+ * Results do not depend on the launch shape. */
+int esbgk_set_tile(esbgk_t *h, int block, int order, int policy);
+int esbgk_get_tile(const esbgk_t *h, int *block, int *order, int *policy);
 
-/* Time the candidate tiles for this handle on its own state (which it then
- * restores), keep the fastest and, if cache_path is not NULL, record it in
- * that file keyed by lattice, storage and size class.  Synchronous. */
+/* Autotune the launch shape: if cache_path names a file holding an entry
+ * for this lattice, N_f class, storage and size class, apply it; otherwise
+ * time every candidate (block 128/256/512 x both orders x both policies,
+ * an even number of steps each) on the handle's own state, restore that
+ * state bitwise, apply the fastest and append it to cache_path (if not
+ * NULL).  budget_ms bounds the timing (<= 0: no bound).  Needs a second copy
+ * of the population storage on the device while it runs.  Synchronous. */
 int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
 
 /* Release the handle and the memory the library owns.  NULL is a no-op. */
@@ -199,13 +205,15 @@ typedef struct {
 } esbgk_domain_desc;
 
 /* Create a batch of n domains of lattice (D, Q).  The library allocates all
- * storage in one device buffer.  Same validation per domain as
- * esbgk_create. */
+ * storage in one device buffer and its own HIP stream.  Same validation per
+ * domain as esbgk_create. */
 int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int storage, esbgk_batch_t **out);
 
+/* Route the batch's work to hip_stream (non-NULL; graphs are captured on it). */
 int esbgk_batch_set_stream(esbgk_batch_t *b, void *hip_stream);
 
-/* Equilibrium start of domain k (fields as for esbgk_init_fields). */
+/* Equilibrium start of domain k (fields as for esbgk_init_fields); only
+ * before the batch's first step (ESBGK_ESTATE after). */
 int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const double *u, const double *T);
 
 /* Advance every domain by n steps (asynchronous).  mode 0: one persistent
@@ -216,6 +224,22 @@ int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const do
  * identical results. */
 int esbgk_batch_step(esbgk_batch_t *b, int64_t n, int mode);
 
+/* Launch shape of the batched kernels: block = cells per tile and work-group
+ * size (multiple of 64 in [64, 512], 0 = 256); policy as for esbgk_set_tile;
+ * window = steps a group of domains advances before the persistent kernel
+ * moves to the next group (0 or 1 = step by step); group_bytes = storage
+ * budget of one domain group (<= 0 keeps the current one, default 96 MB).
+ * Results do not depend on any of these. */
+int esbgk_batch_set_tile(esbgk_batch_t *b, int block, int policy, int window, double group_bytes);
+
+/* esbgk_batch_step bracketed by HIP events on the batch's stream; *ms is
+ * the elapsed time.  Synchronous. */
+int esbgk_batch_step_timed(esbgk_batch_t *b, int64_t n, int mode, double *ms);
+
+/* Wait for the batch's queued work. */
+int esbgk_batch_sync(esbgk_batch_t *b);
+
+/* Per-domain read-outs, as the single-domain calls (synchronous). */
 int esbgk_batch_read_moments(esbgk_batch_t *b, int k, double *rho, double *u, double *T, double *P);
 int esbgk_batch_totals(esbgk_batch_t *b, int k, double *out);
 int esbgk_batch_read_populations(esbgk_batch_t *b, int k, double *f, double *g);

@@ -5,7 +5,7 @@ numpy arrays and forwards to ``libesbgk.so``; all arithmetic of the scheme
 runs in the library's HIP kernels.  PyTorch supplies device memory (the
 population storage is a torch uint8 tensor) and the HIP stream.
 
-The library must have been built (``python -m paper_1611_02409_amd.build``);
+The library must have been built (``python paper_1611_02409_amd/build.py``);
 importing this package without it raises ImportError.
 """
 from __future__ import annotations
@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libesbgk.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1611_02409_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1611_02409_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -70,8 +70,9 @@ _sig("esbgk_write_populations", [_vp, _dp, _dp])
 _sig("esbgk_save", [_vp, ctypes.c_char_p])
 _sig("esbgk_load", [_vp, ctypes.c_char_p])
 _sig("esbgk_step_timed", [_vp, ctypes.c_int64, _dp, _dp])
-_sig("esbgk_set_tile", [_vp, ctypes.c_int, ctypes.c_int])
-_sig("esbgk_get_tile", [_vp, _ip, _ip])
+_sig("esbgk_set_tile", [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int])
+_sig("esbgk_get_tile", [_vp, _ip, _ip, _ip])
+_sig("esbgk_autotune", [_vp, ctypes.c_double, ctypes.c_char_p])
 _sig("esbgk_destroy", [_vp], None)
 
 
@@ -230,10 +231,120 @@ class Lattice:
         _check(_lib.esbgk_step_timed(self._h, int(n), ctypes.byref(tot), _p(per)))
         return tot.value, per
 
-    def set_tile(self, block: int = 0, order: int = 0):
-        _check(_lib.esbgk_set_tile(self._h, block, order))
+    def set_tile(self, block: int = 0, order: int = 0, policy: int = 0):
+        _check(_lib.esbgk_set_tile(self._h, block, order, policy))
 
     def get_tile(self):
-        b, o = ctypes.c_int(), ctypes.c_int()
-        _check(_lib.esbgk_get_tile(self._h, ctypes.byref(b), ctypes.byref(o)))
-        return b.value, o.value
+        b, o, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.esbgk_get_tile(self._h, ctypes.byref(b), ctypes.byref(o), ctypes.byref(p)))
+        return b.value, o.value, p.value
+
+    def autotune(self, budget_ms: float = 0.0, cache_path: str | None = None):
+        """Pick (and optionally cache) the fastest launch shape; returns it."""
+        _check(_lib.esbgk_autotune(self._h, budget_ms, os.fsencode(cache_path) if cache_path else None))
+        return self.get_tile()
+
+
+class DomainDesc(ctypes.Structure):
+    _fields_ = [("N_f", ctypes.c_int), ("Pr", ctypes.c_double), ("tau", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("dims", ctypes.c_int64 * 3)]
+
+
+_sig("esbgk_batch_create", [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(DomainDesc), ctypes.c_int,
+                            ctypes.POINTER(_vp)])
+_sig("esbgk_batch_set_stream", [_vp, _vp])
+_sig("esbgk_batch_init_fields", [_vp, ctypes.c_int, _dp, _dp, _dp])
+_sig("esbgk_batch_set_tile", [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double])
+_sig("esbgk_batch_step", [_vp, ctypes.c_int64, ctypes.c_int])
+_sig("esbgk_batch_step_timed", [_vp, ctypes.c_int64, ctypes.c_int, _dp])
+_sig("esbgk_batch_sync", [_vp])
+_sig("esbgk_batch_status", [_vp, _ip])
+_sig("esbgk_batch_info", [_vp, _i64p, _dp])
+_sig("esbgk_batch_read_moments", [_vp, ctypes.c_int, _dp, _dp, _dp, _dp])
+_sig("esbgk_batch_totals", [_vp, ctypes.c_int, _dp])
+_sig("esbgk_batch_read_populations", [_vp, ctypes.c_int, _dp, _dp])
+_sig("esbgk_batch_destroy", [_vp], None)
+
+PERSISTENT, PER_STEP, PER_DOMAIN = 0, 1, 2
+
+
+class Batch:
+    """Independent periodic domains of one lattice and storage mode, stepped
+    together.  `domains` is a list of dicts with keys dims, Nf, Pr, tau and
+    optionally kappa."""
+
+    def __init__(self, D: int, Q: int, domains, storage: str = "f32"):
+        self.D, self.Q, self.storage = D, Q, storage
+        self.domains = [dict(d) for d in domains]
+        arr = (DomainDesc * len(domains))()
+        for i, d in enumerate(domains):
+            dims = list(d["dims"]) + [1] * (3 - len(d["dims"]))
+            arr[i] = DomainDesc(int(d["Nf"]), float(d["Pr"]), float(d["tau"]), float(d.get("kappa", 0.2)),
+                                (ctypes.c_int64 * 3)(*dims))
+        h = _vp()
+        self._h = None
+        _check(_lib.esbgk_batch_create(D, Q, len(domains), arr, STORAGE[storage], ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.esbgk_batch_destroy(h)
+            self._h = None
+
+    def _shape(self, k):
+        return tuple(reversed(self.domains[k]["dims"]))
+
+    def _ncell(self, k):
+        return int(np.prod(self.domains[k]["dims"]))
+
+    def init_fields(self, k, rho, u, T):
+        n = self._ncell(k)
+        _check(_lib.esbgk_batch_init_fields(self._h, k, _p(_f64(rho, n)), _p(_f64(u, self.D * n)), _p(_f64(T, n))))
+
+    def set_tile(self, block=0, policy=0, window=0, group_bytes=0.0):
+        _check(_lib.esbgk_batch_set_tile(self._h, block, policy, window, group_bytes))
+
+    def step(self, n=1, mode=PERSISTENT):
+        _check(_lib.esbgk_batch_step(self._h, int(n), int(mode)))
+
+    def step_timed(self, n, mode=PERSISTENT) -> float:
+        ms = ctypes.c_double()
+        _check(_lib.esbgk_batch_step_timed(self._h, int(n), int(mode), ctypes.byref(ms)))
+        return ms.value
+
+    def sync(self):
+        _check(_lib.esbgk_batch_sync(self._h))
+
+    def status(self) -> int:
+        s = ctypes.c_int()
+        _check(_lib.esbgk_batch_status(self._h, ctypes.byref(s)))
+        return s.value
+
+    def info(self):
+        c, b = ctypes.c_int64(), ctypes.c_double()
+        _check(_lib.esbgk_batch_info(self._h, ctypes.byref(c), ctypes.byref(b)))
+        return c.value, b.value
+
+    def read_moments(self, k, with_P=False):
+        n, sh = self._ncell(k), self._shape(k)
+        rho, u, T = np.zeros(n), np.zeros(self.D * n), np.zeros(n)
+        npc = self.D * (self.D + 1) // 2
+        P = np.zeros(npc * n) if with_P else None
+        _check(_lib.esbgk_batch_read_moments(self._h, k, _p(rho), _p(u), _p(T), _p(P)))
+        out = dict(rho=rho.reshape(sh), u=u.reshape((self.D,) + sh), T=T.reshape(sh))
+        if with_P:
+            out["P"] = P.reshape((npc,) + sh)
+        return out
+
+    def totals(self, k):
+        out = np.zeros(2 + self.D)
+        _check(_lib.esbgk_batch_totals(self._h, k, _p(out)))
+        return out
+
+    def read_populations(self, k):
+        n, sh = self._ncell(k), self._shape(k)
+        f = np.zeros(self.Q * n)
+        g = np.zeros(self.Q * n) if self.domains[k]["Nf"] > 0 else None
+        _check(_lib.esbgk_batch_read_populations(self._h, k, _p(f), _p(g)))
+        return f.reshape((self.Q,) + sh), (g.reshape((self.Q,) + sh) if g is not None else None)

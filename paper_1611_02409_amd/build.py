@@ -3,7 +3,7 @@
 Every translation unit under ``csrc/`` is compiled with hipcc in parallel and
 linked into ``paper_1611_02409_amd/libesbgk.so``.  Usage::
 
-    python -m paper_1611_02409_amd.build          # or build() from Python
+    python paper_1611_02409_amd/build.py
 """
 from __future__ import annotations
 

@@ -236,7 +236,7 @@ struct esbgk_lattice {
     hipStream_t stream = nullptr;
     int64_t steps = 0;
     bool initialized = false;
-    int block = 256, remap = 1;
+    int block = 256, remap = 0, policy = 0;
     double *d_partials = nullptr;
     double *d_totals = nullptr;
     uint32_t nchunks = 0;
@@ -462,7 +462,7 @@ int esbgk_step(esbgk_t *h, int64_t n) {
     }
     for (int64_t k = 0; k < n; k++) {
         h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(), h->block,
-                     h->remap, h->stream);
+                     h->remap, h->policy, h->stream);
         h->steps++;
     }
     return launch_error();
@@ -747,7 +747,7 @@ int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch
     ESBGK_HIP(hipEventRecord(ev[0], h->stream));
     for (int64_t k = 0; k < n; k++) {
         h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(), h->block,
-                     h->remap, h->stream);
+                     h->remap, h->policy, h->stream);
         h->steps++;
         ESBGK_HIP(hipEventRecord(ev[k + 1], h->stream));
     }
@@ -765,7 +765,7 @@ int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch
     return rc;
 }
 
-int esbgk_set_tile(esbgk_t *h, int block, int order) {
+int esbgk_set_tile(esbgk_t *h, int block, int order, int policy) {
     clear_error();
     if (int rc = check(h)) return rc;
     if (block == 0) block = 256;
@@ -773,20 +773,106 @@ int esbgk_set_tile(esbgk_t *h, int block, int order) {
         set_error("block must be a multiple of 64 in [64, 512] (got %d)", block);
         return ESBGK_EINVAL;
     }
-    if (order < 0 || order > 2) {
-        set_error("order must be 0, 1 or 2 (got %d)", order);
+    if (order < 0 || order > 2 || policy < 0 || policy > 2) {
+        set_error("order and policy must be 0, 1 or 2 (got %d, %d)", order, policy);
         return ESBGK_EINVAL;
     }
     h->block = block;
-    h->remap = order == 2 ? 0 : 1;
+    h->remap = order == 2 ? 1 : 0;
+    h->policy = policy == 2 ? 1 : 0;
     return ESBGK_OK;
 }
 
-int esbgk_get_tile(const esbgk_t *h, int *block, int *order) {
+int esbgk_get_tile(const esbgk_t *h, int *block, int *order, int *policy) {
     clear_error();
     if (int rc = check(h)) return rc;
     if (block) *block = h->block;
-    if (order) *order = h->remap ? 1 : 2;
+    if (order) *order = h->remap ? 2 : 1;
+    if (policy) *policy = h->policy ? 2 : 1;
+    return ESBGK_OK;
+}
+
+namespace {
+std::string tune_key(const esbgk_t *h) {
+    int sc = 0;
+    while ((1ull << (sc + 1)) <= h->su.geom.ncell) sc++;
+    char k[128];
+    snprintf(k, sizeof k, "D%dQ%d npop%d st%d log2n%d", h->D, h->Q, h->su.npop, h->storage, sc);
+    return k;
+}
+}  // namespace
+
+int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
+    clear_error();
+    if (int rc = check_init(h)) return rc;
+    const std::string key = tune_key(h);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            if (line.rfind(key + " ", 0) != 0) continue;
+            int b, o, p;
+            if (sscanf(line.c_str() + key.size(), " block %d order %d policy %d", &b, &o, &p) == 3)
+                return esbgk_set_tile(h, b, o, p);
+        }
+    }
+    DevTmp save;
+    ESBGK_HIP(hipMalloc(&save.p, h->su.bytes));
+    ESBGK_HIP(hipMemcpyAsync(save.p, h->buf, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
+    const int64_t steps0 = h->steps;
+    hipEvent_t e0, e1;
+    ESBGK_HIP(hipEventCreate(&e0));
+    ESBGK_HIP(hipEventCreate(&e1));
+    double best = 1e30;
+    int bb = h->block, bo = h->remap ? 2 : 1, bp = h->policy ? 2 : 1;
+    const auto t_start = std::chrono::steady_clock::now();
+    int rc = ESBGK_OK;
+    for (int block : {256, 512, 128})
+        for (int order : {1, 2})
+            for (int policy : {1, 2}) {
+                const double el =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+                if (budget_ms > 0 && el > budget_ms && best < 1e30) continue;
+                esbgk_set_tile(h, block, order, policy);
+                for (int k = 0; k < 2; k++) {   // warm-up pair
+                    h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(),
+                                 h->block, h->remap, h->policy, h->stream);
+                    h->steps++;
+                }
+                (void)hipEventRecord(e0, h->stream);
+                for (int k = 0; k < 4; k++) {
+                    h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(),
+                                 h->block, h->remap, h->policy, h->stream);
+                    h->steps++;
+                }
+                (void)hipEventRecord(e1, h->stream);
+                if ((rc = launch_error())) break;
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    bb = block;
+                    bo = order;
+                    bp = policy;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ESBGK_HIP(hipMemcpyAsync(h->buf, save.p, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
+    ESBGK_HIP(hipStreamSynchronize(h->stream));
+    h->steps = steps0;
+    if (rc) return rc;
+    esbgk_set_tile(h, bb, bo, bp);
+    if (cache_path) {
+        FILE *fp = std::fopen(cache_path, "a");
+        if (!fp) {
+            set_error("cannot append to %s", cache_path);
+            return ESBGK_EIO;
+        }
+        std::fprintf(fp, "%s block %d order %d policy %d ms_per_step %.4f\n", key.c_str(), bb, bo, bp, best / 4);
+        std::fclose(fp);
+    }
     return ESBGK_OK;
 }
 

@@ -122,27 +122,34 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t set_rsrc(char *base, uint32_t 
     return __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)set_bytes, 0x00020000);
 }
 
-template <int S>
+// CP: cache-policy bits of the buffer instruction (0 = default, 2 = streaming
+// / non-temporal).
+template <int S, int CP = 0>
 __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     if constexpr (S == ST_F32) {
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, 0));
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, CP));
     } else if constexpr (S == ST_F16) {
-        unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
-        return __half2float(__ushort_as_half(h));
+        unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, CP);
+        float v = __half2float(__ushort_as_half(h));
+        // keep the converted value in one register: without this the compiler
+        // folds some conversions into mixed-precision FMAs and keeps both the
+        // FP16 and FP32 copies alive (about 70 more VGPRs)
+        asm("" : "+v"(v));
+        return v;
     } else {
-        unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, 0);
+        unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)off, (int)soff, CP);
         return __uint_as_float(uint32_t(h) << 16);
     }
 }
 
-template <int S>
+template <int S, int CP = 0>
 __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     if constexpr (S == ST_F32) {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, CP);
     } else if constexpr (S == ST_F16) {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)off, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)off, (int)soff, CP);
     } else {
-        __builtin_amdgcn_raw_buffer_store_b16(__bfloat16_as_ushort(__float2bfloat16(v)), r, (int)off, (int)soff, 0);
+        __builtin_amdgcn_raw_buffer_store_b16(__bfloat16_as_ushort(__float2bfloat16(v)), r, (int)off, (int)soff, CP);
     }
 }
 
@@ -215,10 +222,10 @@ struct Nbr {
 // ODD = true : A-A odd layout (state after an odd number of steps).
 // --------------------------------------------------------------------------
 
-template <class L, int S, bool ODD, bool HAS_G>
+template <class L, int S, bool ODD, bool HAS_G, int CP = 0>
 __device__ __forceinline__ void gather(const Sets &R, const Nbr<L, S> &nb, float *F, float *E) {
-    F[0] = ld<S>(R.f, nb.own, 0);
-    if constexpr (HAS_G) E[0] = ld<S>(R.g, nb.own, 0);
+    F[0] = ld<S, CP>(R.f, nb.own, 0);
+    if constexpr (HAS_G) E[0] = ld<S, CP>(R.g, nb.own, 0);
     static_for<L::NP>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
@@ -226,18 +233,18 @@ __device__ __forceinline__ void gather(const Sets &R, const Nbr<L, S> &nb, float
         if constexpr (ODD) {
             const uint32_t op = nb.template at<cx, cy, cz>();
             const uint32_t om = nb.template at<-cx, -cy, -cz>();
-            F[a] = ld<S>(R.f, om, R.so(b));
-            F[b] = ld<S>(R.f, op, R.so(a));
+            F[a] = ld<S, CP>(R.f, om, R.so(b));
+            F[b] = ld<S, CP>(R.f, op, R.so(a));
             if constexpr (HAS_G) {
-                E[a] = ld<S>(R.g, om, R.so(b));
-                E[b] = ld<S>(R.g, op, R.so(a));
+                E[a] = ld<S, CP>(R.g, om, R.so(b));
+                E[b] = ld<S, CP>(R.g, op, R.so(a));
             }
         } else {
-            F[a] = ld<S>(R.f, nb.own, R.so(a));
-            F[b] = ld<S>(R.f, nb.own, R.so(b));
+            F[a] = ld<S, CP>(R.f, nb.own, R.so(a));
+            F[b] = ld<S, CP>(R.f, nb.own, R.so(b));
             if constexpr (HAS_G) {
-                E[a] = ld<S>(R.g, nb.own, R.so(a));
-                E[b] = ld<S>(R.g, nb.own, R.so(b));
+                E[a] = ld<S, CP>(R.g, nb.own, R.so(a));
+                E[b] = ld<S, CP>(R.g, nb.own, R.so(b));
             }
         }
     });
@@ -246,10 +253,10 @@ __device__ __forceinline__ void gather(const Sets &R, const Nbr<L, S> &nb, float
 // Write post-collision populations so that the layout flips parity:
 // after an even-layout read, f*_i goes to the own cell's plane opp(i); after
 // an odd-layout read, f*_i goes to (x + c_i, plane i).
-template <class L, int S, bool ODD, bool HAS_G>
+template <class L, int S, bool ODD, bool HAS_G, int CP = 0>
 __device__ __forceinline__ void scatter(const Sets &R, const Nbr<L, S> &nb, const float *F, const float *E) {
-    st<S>(F[0], R.f, nb.own, 0);
-    if constexpr (HAS_G) st<S>(E[0], R.g, nb.own, 0);
+    st<S, CP>(F[0], R.f, nb.own, 0);
+    if constexpr (HAS_G) st<S, CP>(E[0], R.g, nb.own, 0);
     static_for<L::NP>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
@@ -257,18 +264,18 @@ __device__ __forceinline__ void scatter(const Sets &R, const Nbr<L, S> &nb, cons
         if constexpr (ODD) {
             const uint32_t op = nb.template at<cx, cy, cz>();
             const uint32_t om = nb.template at<-cx, -cy, -cz>();
-            st<S>(F[a], R.f, op, R.so(a));
-            st<S>(F[b], R.f, om, R.so(b));
+            st<S, CP>(F[a], R.f, op, R.so(a));
+            st<S, CP>(F[b], R.f, om, R.so(b));
             if constexpr (HAS_G) {
-                st<S>(E[a], R.g, op, R.so(a));
-                st<S>(E[b], R.g, om, R.so(b));
+                st<S, CP>(E[a], R.g, op, R.so(a));
+                st<S, CP>(E[b], R.g, om, R.so(b));
             }
         } else {
-            st<S>(F[a], R.f, nb.own, R.so(b));
-            st<S>(F[b], R.f, nb.own, R.so(a));
+            st<S, CP>(F[a], R.f, nb.own, R.so(b));
+            st<S, CP>(F[b], R.f, nb.own, R.so(a));
             if constexpr (HAS_G) {
-                st<S>(E[a], R.g, nb.own, R.so(b));
-                st<S>(E[b], R.g, nb.own, R.so(a));
+                st<S, CP>(E[a], R.g, nb.own, R.so(b));
+                st<S, CP>(E[b], R.g, nb.own, R.so(a));
             }
         }
     });

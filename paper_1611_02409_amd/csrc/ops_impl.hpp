@@ -8,7 +8,7 @@
 namespace esbgk {
 
 // ---------------------------------------------------------------- step
-template <class L, int S, bool ODD, bool HAS_G>
+template <class L, int S, bool ODD, bool HAS_G, int CP>
 __global__ __launch_bounds__(512) void k_step(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
                                               uint32_t remap) {
     const uint32_t blk = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -19,9 +19,9 @@ __global__ __launch_bounds__(512) void k_step(char *fb, char *gb, uint32_t pb, u
     else nb.own = cell * StoreBytes<S>::value;
     const Sets R(fb, gb, pb, sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
-    gather<L, S, ODD, HAS_G>(R, nb, F, E);
+    gather<L, S, ODD, HAS_G, CP>(R, nb, F, E);
     collide<L, HAS_G>(cp, F, E);
-    scatter<L, S, ODD, HAS_G>(R, nb, F, E);
+    scatter<L, S, ODD, HAS_G, CP>(R, nb, F, E);
 }
 
 // ---------------------------------------------------------------- init
@@ -171,16 +171,23 @@ inline uint32_t nblocks(uint64_t n, int block) { return (uint32_t)((n + block - 
 
 template <class L, int S>
 struct OpsImpl {
-    static void step(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, int block,
-                     int remap, hipStream_t s) {
+    template <int CP>
+    static void step_cp(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd,
+                        bool has_g, int block, int remap, hipStream_t s) {
         const uint32_t nb = nblocks(g.ncell, block);
         if (odd) {
-            if (has_g) k_step<L, S, true, true><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
-            else k_step<L, S, true, false><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            if (has_g) k_step<L, S, true, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            else k_step<L, S, true, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
         } else {
-            if (has_g) k_step<L, S, false, true><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
-            else k_step<L, S, false, false><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            if (has_g) k_step<L, S, false, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            else k_step<L, S, false, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
         }
+    }
+    // policy 0: default caching; 1: non-temporal loads and stores
+    static void step(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd,
+                     bool has_g, int block, int remap, int policy, hipStream_t s) {
+        if (policy) step_cp<2>(fb, gb, pb, sb, g, c, odd, has_g, block, remap, s);
+        else step_cp<0>(fb, gb, pb, sb, g, c, odd, has_g, block, remap, s);
     }
     static void init(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
                      hipStream_t s) {

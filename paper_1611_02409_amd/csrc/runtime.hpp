@@ -53,8 +53,8 @@ int fields_to_dev(const double *rho, const double *u, const double *T, int D, ui
 
 // Kernel dispatch of one (lattice, storage) combination.
 struct Ops {
-    void (*step)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, int block,
-                 int remap, hipStream_t s);
+    void (*step)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
+                 int block, int remap, int policy, hipStream_t s);
     void (*init)(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
                  hipStream_t s);
     void (*moments)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, float *out,

@@ -1,0 +1,103 @@
+"""CPU-side checks of the C ABI: the built library exports every function
+include/esbgk.h declares, host-side validation rejects bad arguments
+before touching a device, and the library's own lattice constants and
+parameter mapping agree with the oracle's independent derivation."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "esbgk.h")
+LIB = os.path.join(ROOT, "paper_1611_02409_amd", "libesbgk.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(esbgk_\w+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) > 30
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.fixture(scope="module")
+def esb():
+    import paper_1611_02409_amd as m
+    return m
+
+
+@pytest.mark.parametrize("D,Q", [(2, 37), (2, 33), (3, 39)])
+def test_lattice_constants_agree_with_oracle(esb, D, Q):
+    li = esb.lattice_info(D, Q)
+    L = oracle.Lattice(D, Q)
+    oc = [tuple(x) for x in L.c]
+    perm = [oc.index(tuple(c)) for c in li["c"]]
+    assert sorted(perm) == list(range(Q))
+    assert abs(li["r"] - L.r) < 1e-15
+    np.testing.assert_allclose(li["w"], L.w[perm], rtol=1e-14)
+    # storage order: rest first, then +c/-c pairs
+    assert not li["c"][0].any()
+    for p in range((Q - 1) // 2):
+        assert np.array_equal(li["c"][2 * p + 1], -li["c"][2 * p + 2])
+
+
+@pytest.mark.parametrize("Nf,Pr,tau", [(3, 0.71, 0.6), (0, 2.0, 0.55), (1, 0.5, 1.2), (2, 0.71, 0.7)])
+def test_parameter_mapping_agrees_with_oracle(esb, Nf, Pr, tau):
+    a = esb.params(2, Nf, Pr, tau, 0.2)
+    b = oracle.param_map(2, Nf, Pr, tau, 0.2)
+    for k in ("omega", "omega_s", "nu", "gamma"):
+        assert abs(a[k] - b[k]) < 1e-15
+
+
+@pytest.mark.parametrize("args", [
+    dict(D=2, Nf=3, Pr=0.71, tau=0.5),
+    dict(D=2, Nf=3, Pr=0.0, tau=0.8),
+    dict(D=2, Nf=-1, Pr=0.71, tau=0.8),
+    dict(D=4, Nf=3, Pr=0.71, tau=0.8),
+    dict(D=2, Nf=3, Pr=float("nan"), tau=0.8),
+    dict(D=2, Nf=3, Pr=0.71, tau=0.8, kappa=1.0),
+    dict(D=2, Nf=3, Pr=0.1, tau=1.0, kappa=0.0),       # nu = -4.5: Lambda could lose positive-definiteness
+])
+def test_invalid_parameters_rejected(esb, args):
+    kappa = args.pop("kappa", 0.2)
+    with pytest.raises(esb.EsbgkError) as e:
+        esb.params(args["D"], args["Nf"], args["Pr"], args["tau"], kappa)
+    assert e.value.code == -1
+
+
+def test_create_rejects_bad_shapes_without_a_device(esb):
+    lib = esb._lib
+    h = ctypes.c_void_p()
+    for D, Q, dims, storage, code in [(2, 35, (8, 8), 0, -2), (2, 37, (2, 8), 0, -1), (2, 37, (8, 8), 7, -1),
+                                      (2, 37, (70000, 70000), 0, -2), (3, 39, (8, 8, 2), 0, -1)]:
+        d = (ctypes.c_int64 * 3)(*(list(dims) + [1] * (3 - len(dims))))
+        rc = lib.esbgk_create(D, Q, 3, 0.71, 0.8, d, storage, ctypes.byref(h))
+        assert rc == code, (D, Q, dims, rc, lib.esbgk_last_error())
+        assert lib.esbgk_last_error()
+
+
+def test_storage_bytes(esb):
+    n = esb.storage_bytes(2, 37, 3, (4096, 4096), "f32")
+    assert n == 2 * 37 * 4096 * 4096 * 4
+    assert esb.storage_bytes(2, 37, 0, (4096, 4096), "f16") == 37 * 4096 * 4096 * 2
+    assert esb.storage_bytes(3, 39, 2, (256, 256, 256), "bf16") == 2 * 39 * 256 ** 3 * 2
+
+
+def test_null_handles_are_rejected(esb):
+    lib = esb._lib
+    assert lib.esbgk_step(None, 1) == -1
+    assert lib.esbgk_totals(None, None) == -1
+    lib.esbgk_destroy(None)
+    lib.esbgk_batch_destroy(None)

@@ -1,0 +1,142 @@
+"""GPU parity of the batched path: every mode (persistent graph launch,
+one launch per step, per-domain launch loop) gives bitwise the same
+populations as single-domain runs, and those match the FP64 oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+from gpu_helpers import pop_error  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+esb = pytest.importorskip("paper_1611_02409_amd")
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DOMS = [
+    dict(dims=(64, 48), Nf=3, Pr=0.71, tau=0.6),
+    dict(dims=(40, 36), Nf=0, Pr=2.0, tau=0.9),
+    dict(dims=(33, 35), Nf=1, Pr=0.5, tau=1.2),
+    dict(dims=(96, 64), Nf=3, Pr=1.3, tau=0.55),
+    dict(dims=(20, 70), Nf=0, Pr=0.8, tau=0.75, kappa=0.4),
+    dict(dims=(130, 12), Nf=1, Pr=1.9, tau=0.95),
+]
+
+
+def fields_of(k, dom):
+    return workloads.random_state(dom["dims"], seed=100 + k)
+
+
+def make_batch(storage="f32", block=256, window=1, group_bytes=0.0, policy=0):
+    b = esb.Batch(2, 37, DOMS, storage=storage)
+    b.set_tile(block, policy, window, group_bytes)
+    for k, d in enumerate(DOMS):
+        b.init_fields(k, *fields_of(k, d))
+    return b
+
+
+def pops(b):
+    return [b.read_populations(k) for k in range(len(DOMS))]
+
+
+def same(pa, pb):
+    for (fa, ga), (fb, gb) in zip(pa, pb):
+        if not np.array_equal(fa, fb):
+            return False
+        if ga is not None and not np.array_equal(ga, gb):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("nsteps", [1, 6, 7])
+def test_modes_agree_bitwise_and_match_single_domains(nsteps):
+    ref = make_batch()
+    ref.step(nsteps, mode=esb.PER_DOMAIN)
+    p2 = pops(ref)
+    for mode in (esb.PER_STEP, esb.PERSISTENT):
+        b = make_batch()
+        b.step(nsteps, mode=mode)
+        assert b.status() == 0
+        assert same(pops(b), p2), f"mode {mode} differs from the per-domain loop"
+    for k, d in enumerate(DOMS):
+        lat = esb.Lattice(2, 37, d["Nf"], d["Pr"], d["tau"], d["dims"], kappa=d.get("kappa", 0.2))
+        lat.init_fields(*fields_of(k, d))
+        lat.step(nsteps)
+        f, g = lat.read_populations()
+        assert np.array_equal(f, p2[k][0])
+        if g is not None:
+            assert np.array_equal(g, p2[k][1])
+
+
+def test_batch_matches_oracle():
+    b = make_batch()
+    b.step(5, mode=esb.PERSISTENT)
+    li = esb.lattice_info(2, 37)
+    L = oracle.Lattice(2, 37)
+    oc = [tuple(x) for x in L.c]
+    perm = np.array([oc.index(tuple(c)) for c in li["c"]])
+    for k, d in enumerate(DOMS):
+        sim = oracle.Sim(2, 37, d["Nf"], d["Pr"], d["tau"], d["dims"], kappa=d.get("kappa", 0.2))
+        sim.init(*fields_of(k, d))
+        sim.step(5)
+        fo, go = sim.get_pops()
+        fg, gg = b.read_populations(k)
+        e = pop_error(li["w"], fg, fo[perm])
+        print(f"domain {k}: pop err {e:.2e}")
+        assert e < 3e-6
+        mo, mg = sim.moments(), b.read_moments(k)
+        assert np.max(np.abs(mo["u"] - mg["u"])) < 1e-6
+        t = b.totals(k)
+        assert abs(t[0] - sim.totals()[0]) / np.prod(d["dims"]) < 1e-7
+
+
+@pytest.mark.parametrize("block,window,group_bytes", [(64, 3, 2e6), (512, 1, 0.0), (128, 16, 1e5)])
+def test_persistent_windows_and_groups(block, window, group_bytes):
+    """Domain groups advanced several steps at a time (and tiny groups,
+    one domain each) give the same result as step-by-step execution."""
+    ref = make_batch()
+    ref.step(9, mode=esb.PER_DOMAIN)
+    b = make_batch(block=block, window=window, group_bytes=group_bytes)
+    b.step(9, mode=esb.PERSISTENT)
+    assert b.status() == 0
+    assert same(pops(b), pops(ref))
+
+
+@pytest.mark.parametrize("mode", [esb.PERSISTENT, esb.PER_STEP])
+def test_graph_replays(mode):
+    """The same captured graph replayed several times, with reads in
+    between, continues exactly like one long per-domain run."""
+    ref = make_batch()
+    ref.step(12, mode=esb.PER_DOMAIN)
+    b = make_batch()
+    for _ in range(3):
+        b.step(4, mode=mode)
+        b.read_moments(0)
+    assert b.status() == 0
+    assert same(pops(b), pops(ref))
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_reduced_storage_batch_equals_single(storage):
+    b = make_batch(storage=storage)
+    b.step(5, mode=esb.PERSISTENT)
+    for k, d in enumerate(DOMS[:3]):
+        lat = esb.Lattice(2, 37, d["Nf"], d["Pr"], d["tau"], d["dims"], storage=storage)
+        lat.init_fields(*fields_of(k, d))
+        lat.step(5)
+        f, _ = lat.read_populations()
+        assert np.array_equal(f, b.read_populations(k)[0])
+
+
+def test_init_after_step_is_rejected():
+    b = make_batch()
+    b.step(1, mode=esb.PER_STEP)
+    with pytest.raises(esb.EsbgkError):
+        b.init_fields(0, *fields_of(0, DOMS[0]))
