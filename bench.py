@@ -1,0 +1,222 @@
+"""Benchmark of the ES-BGK stream-collide step on one MI355X.
+
+Prints one JSON line.  The headline workload is a 4096 x 4096 periodic D2Q37
+domain with both populations stored in FP32 (N_f = 3, Pr = 0.71, tau = 0.6,
+superposed shear and thermal waves plus seeded noise); a step is one fused
+stream-collide launch over the whole grid with inputs resident in HBM.
+`value` is million lattice-cell updates per second (MLUPS) over exactly
+--steps timed steps.  Variants (FP16/BF16 deviation storage, the batched
+256-domain workload in its three execution modes, D3Q39 at 256^3) are
+reported beside it, each with its own HBM-roofline fraction.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-variants] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS and % of HBM peak, FP32 vs FP16-storage vs batched, at stated error vs FP64"
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_d2q37_f32_4096_traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "ops_impl.hpp"):
+        with open(os.path.join(ROOT, "paper_1611_02409_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_cell(Q, npop, storage):
+    return 2 * Q * npop * (4 if storage == "f32" else 2)
+
+
+def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, warmup, tune_cache):
+    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage)
+    lat.init_fields(*fields)
+    tile = lat.autotune(cache_path=tune_cache)
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    total_ms, per = lat.step_timed(steps)       # HIP events around every launch, on the lattice's stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ncell = int(np.prod(dims))
+    # after `warmup` steps the first timed launch has parity warmup % 2
+    first_odd = warmup % 2 == 1
+    odd = per[0::2] if first_odd else per[1::2]
+    even = per[1::2] if first_odd else per[0::2]
+    return dict(lat=lat, tile=tile, total_ms=total_ms, wall_s=wall, ncell=ncell,
+                mlups=ncell * steps / (total_ms * 1e-3) / 1e6, odd_ms=float(np.mean(odd)),
+                even_ms=float(np.mean(even)))
+
+
+def roofline(bytes_per_launch, launch_ms, peak=HBM_PEAK_GBS, traffic=None):
+    ach = bytes_per_launch / (launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": peak, "unit": "GB/s", "frac": round(ach / peak, 4),
+            "traffic": traffic}
+
+
+def measured_traffic(bytes_per_launch):
+    """HBM bytes per launch of the odd step kernel from the committed
+    rocprofv3 counter summary, if it was taken from the current kernel
+    source; otherwise None."""
+    try:
+        with open(PROFILE_TRAFFIC) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(seconds=12.0):
+    """The FP64 oracle on the host: D2Q37, N_f = 3, 1024^2 periodic, same
+    initial recipe, as many whole steps as fit in about `seconds`."""
+    import oracle
+    import workloads
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    n = 1024
+    sim = oracle.Sim(2, 37, 3, 0.71, 0.6, (n, n))
+    sim.init(*workloads.waves_noise_2d(n))
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        sim.step(1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds or steps >= 200:
+            break
+    return {"value": round(n * n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, D2Q37 1024x1024 periodic, N_f=3, Pr=0.71, tau=0.6, {steps} steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=200)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (the batched and single-domain paths have no "
+              "multi-GPU mode); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1611_02409_amd as esb
+    import workloads
+
+    tune_cache = os.path.join(ROOT, "profiles", "autotune_cache.txt")
+    N = 4096
+    D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
+    fields = workloads.waves_noise_2d(N)
+    ceiling = esb.stream_ceiling(N * N, 10)
+
+    main_run = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), "f32", fields, args.steps, args.warmup, tune_cache)
+    bpl = bytes_per_cell(Q, 2, "f32") * N * N
+    roof = roofline(bpl, main_run["odd_ms"], traffic=measured_traffic(bpl))
+    roof["kernel"] = "k_step<D2Q37, FP32, odd layout> (the slower of the two A-A kernels)"
+    roof["bytes_per_launch"] = bpl
+    roof["avg_launch_ms"] = round(main_run["odd_ms"], 4)
+    roof["even_kernel"] = {"avg_launch_ms": round(main_run["even_ms"], 4),
+                           "achieved": round(bpl / (main_run["even_ms"] * 1e-3) / 1e9, 1)}
+    roof["measured_stream_ceiling_GBs"] = round(ceiling, 1)
+    roof["frac_of_measured_ceiling"] = round(bpl / (main_run["odd_ms"] * 1e-3) / 1e9 / ceiling, 4)
+    step_ms = main_run["total_ms"] / args.steps
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "D2Q37 4096x4096 periodic, f and g populations FP32 SoA, N_f=3 (gamma=1.4), "
+                               "Pr=0.71, tau=0.6, kappa=0.2, shear+thermal waves (amplitude 1e-3) + N(0,1e-5^2) "
+                               "noise seed 1611",
+                   "lattice": "D2Q37", "grid": [N, N], "storage": "f32", "N_f": Nf, "Pr": Pr, "tau": tau,
+                   "tile": {"block": main_run["tile"][0], "order": main_run["tile"][1],
+                            "policy": main_run["tile"][2]},
+                   "algorithmic_bytes_per_cell_step": bytes_per_cell(Q, 2, "f32"),
+                   "hbm_GBs_per_step_avg": round(bpl / (step_ms * 1e-3) / 1e9, 1)},
+        "roofline": roof,
+    }
+    del main_run
+    torch.cuda.empty_cache()
+
+    if not args.no_variants:
+        var = {}
+        for storage in ("f16", "bf16"):
+            r = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), storage, fields, args.steps, args.warmup, tune_cache)
+            b = bytes_per_cell(Q, 2, storage) * N * N
+            var[f"d2q37_4096_{storage}_dev"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / args.steps, 4),
+                                                "roofline_frac_odd": round(b / (r["odd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                                "GBs_per_step": round(b / (r["total_ms"] / args.steps * 1e-3) / 1e9, 1),
+                                                "tile": r["tile"]}
+            del r
+            torch.cuda.empty_cache()
+        del fields
+        # D3Q39 256^3 thermal Taylor-Green vortex, FP32
+        n3 = 256
+        f3 = workloads.taylor_green_3d(n3)
+        r = time_single(esb, torch, 3, 39, 2, 0.71, 0.7, (n3, n3, n3), "f32", f3, max(50, args.steps // 2),
+                        args.warmup, tune_cache)
+        b = bytes_per_cell(39, 2, "f32") * n3 ** 3
+        s3 = max(50, args.steps // 2)
+        var["d3q39_256cube_f32"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / s3, 4),
+                                    "roofline_frac_odd": round(b / (r["odd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                    "GBs_per_step": round(b / (r["total_ms"] / s3 * 1e-3) / 1e9, 1), "tile": r["tile"]}
+        del r, f3
+        torch.cuda.empty_cache()
+        # batched: 256 independent domains
+        doms = workloads.batch_domains(256)
+        bt = esb.Batch(2, 37, [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms])
+        for k, d in enumerate(doms):
+            bt.init_fields(k, *workloads.batch_fields(d))
+        cells, bps = bt.info()
+        res = {}
+        for mode, name in ((0, "persistent_graph"), (1, "graph_per_step"), (2, "per_domain_loop")):
+            n = args.batch_steps if mode != 2 else max(20, args.batch_steps // 5)
+            bt.step(n, mode)          # warm-up (captures the graph)
+            torch.cuda.synchronize()
+            ms = bt.step_timed(n, mode)
+            if bt.status() != 0:
+                raise RuntimeError("persistent batch kernel reported a timed-out wait")
+            res[name] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1), "steps": n,
+                         "GBs": round(bps * n / (ms * 1e-3) / 1e9, 1),
+                         "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        res["cells"] = cells
+        res["domains"] = len(doms)
+        res["speedup_vs_per_domain_loop"] = round(res["persistent_graph"]["mlups"] / res["per_domain_loop"]["mlups"], 3)
+        var["batched_256_d2q37_f32"] = res
+        del bt
+        out["variants"] = var
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

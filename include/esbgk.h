@@ -189,6 +189,13 @@ int esbgk_get_tile(const esbgk_t *h, int *block, int *order, int *policy);
  * of the population storage on the device while it runs.  Synchronous. */
 int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
 
+/* Measured ceiling of the step kernels' memory pattern: an in-place read and
+ * write of 74 FP32 planes of `cells` cells (1 <= reps timed launches, on the
+ * default stream, 256 <= cells <= 2.8e7) with no arithmetic; *gbps counts
+ * read plus written bytes.  Allocates and frees its own buffer.  A roofline
+ * reference next to the published HBM peak, not part of the scheme. */
+int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps);
+
 /* Release the handle and the memory the library owns.  NULL is a no-op. */
 void esbgk_destroy(esbgk_t *h);
 

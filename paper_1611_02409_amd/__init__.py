@@ -74,6 +74,14 @@ _sig("esbgk_set_tile", [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int])
 _sig("esbgk_get_tile", [_vp, _ip, _ip, _ip])
 _sig("esbgk_autotune", [_vp, ctypes.c_double, ctypes.c_char_p])
 _sig("esbgk_destroy", [_vp], None)
+_sig("esbgk_stream_ceiling", [ctypes.c_int64, ctypes.c_int, _dp])
+
+
+def stream_ceiling(cells: int = 4096 * 4096, reps: int = 10) -> float:
+    """GB/s of an arithmetic-free in-place read+write of 74 FP32 planes."""
+    out = ctypes.c_double()
+    _check(_lib.esbgk_stream_ceiling(int(cells), int(reps), ctypes.byref(out)))
+    return out.value
 
 
 def _check(rc: int):
