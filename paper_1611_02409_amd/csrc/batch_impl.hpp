@@ -125,11 +125,20 @@ __global__ __launch_bounds__(512) void k_batch_persistent(char *base, BatchDev b
         const uint32_t d = b.tile_dom[k];
         const DomDev &dd = b.doms[d];
         if (threadIdx.x == 0 && s > 0) {
+            // bounded wait: about 2^20 polls (well under a second); every 256
+            // polls also look at the launch-wide abort flag so that one
+            // timed-out wait stops every work-group quickly
             const uint32_t need = s * dd.ntiles;
             uint32_t spins = 0;
             while (__hip_atomic_load(b.done + d, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1u << 24)) {
+                __builtin_amdgcn_s_sleep(2);
+                ++spins;
+                if ((spins & 255u) == 0 &&
+                    __hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    sh_abort = 1;
+                    break;
+                }
+                if (spins > (1u << 20)) {
                     __hip_atomic_store(b.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     sh_abort = 1;
                     break;
