@@ -224,8 +224,8 @@ int esbgk_batch_set_stream(esbgk_batch_t *b, void *hip_stream);
 int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const double *u, const double *T);
 
 /* Advance every domain by n steps (asynchronous).  mode 0: one persistent
- * kernel launch that loops over all n steps (per-domain step ordering is
- * kept by device-side counters; launched through a captured HIP graph);
+ * kernel launch that loops over all n steps (consecutive steps are ordered
+ * by grid-wide barriers; launched through a captured HIP graph);
  * mode 1: one launch per step covering every domain; mode 2: one launch per
  * domain per step (the per-domain loop baseline).  All modes give bitwise
  * identical results. */
@@ -235,7 +235,8 @@ int esbgk_batch_step(esbgk_batch_t *b, int64_t n, int mode);
  * size (multiple of 64 in [64, 512], 0 = 256); policy as for esbgk_set_tile;
  * window = steps a group of domains advances before the persistent kernel
  * moves to the next group (0 or 1 = step by step); group_bytes = storage
- * budget of one domain group (<= 0 keeps the current one, default 96 MB).
+ * budget of one domain group (<= 0 keeps the current one; default: all
+ * domains form one group).
  * Results do not depend on any of these. */
 int esbgk_batch_set_tile(esbgk_batch_t *b, int block, int policy, int window, double group_bytes);
 
@@ -255,9 +256,9 @@ int esbgk_batch_read_populations(esbgk_batch_t *b, int k, double *f, double *g);
  * (read + write) over all domains. */
 int esbgk_batch_info(const esbgk_batch_t *b, int64_t *cells, double *bytes_per_step);
 
-/* Persistent-kernel diagnostics of the last mode-0 call: *status 0 = ran to
- * completion, 1 = a bounded wait timed out (the kernel then stopped early
- * and the state is invalid). */
+/* Persistent-kernel diagnostics of the last mode-0 call (synchronous):
+ * *status 0 = ran to completion, 1 = a bounded barrier wait timed out (the
+ * kernel then stopped early and the state is invalid). */
 int esbgk_batch_status(esbgk_batch_t *b, int *status);
 
 void esbgk_batch_destroy(esbgk_batch_t *b);

@@ -15,12 +15,8 @@ const BatchOps *batch_ops_d3q39(int storage);
 
 // Zero the launch's counters (a plain kernel, so the reset can live inside a
 // captured graph).
-static __global__ void k_batch_reset(uint32_t *ticket, uint32_t *done, uint32_t ndom, uint32_t *status) {
-    for (uint32_t i = threadIdx.x; i < ndom; i += blockDim.x) done[i] = 0;
-    if (threadIdx.x == 0) {
-        *ticket = 0;
-        *status = 0;
-    }
+static __global__ void k_batch_reset(uint32_t *ctr) {
+    if (threadIdx.x < 2) ctr[threadIdx.x] = 0;
 }
 
 static const BatchOps *get_batch_ops(int D, int Q, int storage) {
@@ -49,12 +45,12 @@ struct esbgk_batch {
     // launch shape
     int block = 256, policy = 0;
     uint32_t window = 1;
-    double group_bytes = 96e6;
+    double group_bytes = 1e30;   // one group: every step covers all domains
     // device tables
     DomDev *d_doms = nullptr;
     uint32_t *d_tile_dom = nullptr, *d_tile_cell = nullptr;
     GroupDev *d_groups = nullptr;
-    uint32_t *d_ctr = nullptr;   // [ticket, status, done[n]]
+    uint32_t *d_ctr = nullptr;   // [barrier arrivals, status]
     uint32_t tiles = 0, ngroups = 0;
     int tables_block = -1;
     // captured graphs keyed by (mode, n, parity, block, policy, window)
@@ -168,7 +164,7 @@ void enqueue(esbgk_batch_t *b, int64_t n, int mode, uint32_t grid) {
             b->bops->step(b->buf, b->d_doms, b->d_tile_dom, b->d_tile_cell, b->tiles, b->block,
                           ((b->steps + s) & 1) != 0, b->policy, b->stream);
     } else {
-        k_batch_reset<<<1, 256, 0, b->stream>>>(b->d_ctr, b->d_ctr + 2, (uint32_t)b->n, b->d_ctr + 1);
+        k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_ctr);
         BatchDev bd{};
         bd.doms = b->d_doms;
         bd.tile_dom = b->d_tile_dom;
@@ -179,9 +175,8 @@ void enqueue(esbgk_batch_t *b, int64_t n, int mode, uint32_t grid) {
         bd.nsteps = (uint32_t)n;
         bd.window = b->window;
         bd.parity0 = (uint32_t)(b->steps & 1);
-        bd.ticket = b->d_ctr;
+        bd.arrive = b->d_ctr;
         bd.status = b->d_ctr + 1;
-        bd.done = b->d_ctr + 2;
         b->bops->persistent(b->buf, bd, grid, b->block, b->policy, b->stream);
     }
 }
@@ -260,7 +255,8 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
             break;
         }
         if (hipMalloc(&b->d_doms, sizeof(DomDev) * n) != hipSuccess ||
-            hipMalloc(&b->d_ctr, sizeof(uint32_t) * (2 + n)) != hipSuccess) {
+            hipMalloc(&b->d_ctr, sizeof(uint32_t) * 2) != hipSuccess ||
+            hipMemsetAsync(b->d_ctr, 0, sizeof(uint32_t) * 2, b->stream) != hipSuccess) {
             set_error("device allocation of batch tables failed");
             rc = ESBGK_ENOMEM;
             break;

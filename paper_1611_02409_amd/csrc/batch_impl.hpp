@@ -1,18 +1,20 @@
 // Batched stream-collide over many independent periodic domains.
 //
 // Work unit: a tile of `block` consecutive cells of one domain.  The tiles of
-// all domains form one list per step (domain by domain).
+// all domains form one list per step (domain by domain); consecutive domains
+// are grouped so that a group's storage fits a byte budget.
 //
-// Persistent mode: one launch of co-resident work-groups that claim tickets
-// from a global counter.  Tickets enumerate (step, tile) items in windows of
-// W steps: within a window, domain group by domain group (groups are runs of
-// consecutive domains whose storage fits a byte budget), and within a group
-// step by step.  A work-group may start tile k of domain d at step s only
-// when domain d has finished every tile of step s-1 (a per-domain counter of
-// finished tiles, released/acquired at device scope).  Every wait is on an
-// item with a smaller ticket, so the earliest unfinished ticket can always
-// proceed; the waits are also bounded, and a timed-out wait stops the launch
-// with a status flag instead of hanging.
+// Persistent mode: one launch of co-resident work-groups loops over windows
+// of W steps; inside a window it takes one domain group at a time through
+// its W steps.  Each (group, step) is split over the work-groups by a
+// grid-stride loop over the group's tiles and closed by a grid-wide barrier:
+// every wave drains its stores, the work-group's first thread writes back
+// the XCD's L2 (release at device scope), arrives on a global counter and
+// polls it with relaxed loads; once all work-groups have arrived it
+// invalidates its caches (acquire) once.  A-A streaming needs exactly this
+// ordering between consecutive steps of one domain.  The wait is bounded by
+// the shader clock; a timeout sets a status flag, and every work-group that
+// sees the flag leaves, so the launch always drains.
 #pragma once
 
 #include "runtime.hpp"
@@ -42,10 +44,27 @@ struct BatchDev {
     uint32_t nsteps;              // steps of this launch
     uint32_t window;              // W
     uint32_t parity0;             // parity of the step count at launch
-    uint32_t *ticket;             // global ticket counter
-    uint32_t *done;               // per-domain finished tiles
-    uint32_t *status;             // 0 ok, 1 timed out
+    uint32_t *arrive;             // grid-barrier arrival counter
+    uint32_t *status;             // 0 ok, 1 a barrier wait timed out
 };
+
+// A record every lane of the wave reads at the same address, returned in
+// scalar registers (the compiler cannot prove that a table load is uniform;
+// without this every population access becomes a waterfall loop over a
+// per-lane buffer descriptor).
+template <class T>
+__device__ __forceinline__ T uniform_load(const T *p) {
+    static_assert(sizeof(T) % 4 == 0, "record must be a whole number of words");
+    uint32_t w[sizeof(T) / 4];
+    __builtin_memcpy(w, p, sizeof(T));
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; i++) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    T out;
+    __builtin_memcpy(&out, w, sizeof(T));
+    return out;
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(const uint32_t *p) { return __builtin_amdgcn_readfirstlane(*p); }
 
 // Process one tile of one domain at the given parity.
 template <class L, int S, int CP, bool ODD, bool HAS_G>
@@ -77,81 +96,62 @@ template <class L, int S, int CP>
 __global__ __launch_bounds__(512) void k_batch_step(char *base, const DomDev *doms, const uint32_t *tile_dom,
                                                     const uint32_t *tile_cell, uint32_t odd) {
     const uint32_t t = blockIdx.x;
-    const DomDev &dd = doms[tile_dom[t]];
-    tile_dispatch<L, S, CP>(base, dd, tile_cell[t] + threadIdx.x, odd != 0);
+    const DomDev dd = uniform_load(doms + uniform_u32(tile_dom + t));
+    tile_dispatch<L, S, CP>(base, dd, uniform_u32(tile_cell + t) + threadIdx.x, odd != 0);
 }
 
-// Map a ticket to (step within the launch, tile).
-__device__ __forceinline__ void ticket_item(const BatchDev &b, uint32_t t, uint32_t &step, uint32_t &tile) {
-    const uint64_t per_window = (uint64_t)b.window * b.tiles;
-    const uint32_t nfull = b.nsteps / b.window;
-    uint32_t w0, W;
-    uint64_t r;
-    if ((uint64_t)t < (uint64_t)nfull * per_window) {
-        w0 = (uint32_t)(t / per_window) * b.window;
-        r = t % per_window;
-        W = b.window;
-    } else {
-        w0 = nfull * b.window;
-        r = (uint64_t)t - (uint64_t)nfull * per_window;
-        W = b.nsteps - w0;
-    }
-    // groups are laid out consecutively, each taking W * (its tiles) tickets
-    uint32_t g = 0;
-    for (; g + 1 < b.ngroups; g++)
-        if (r < (uint64_t)W * b.groups[g + 1].tile_begin) break;
-    const uint32_t tb = b.groups[g].tile_begin, tg = b.groups[g].tile_end - tb;
-    const uint64_t local = r - (uint64_t)W * tb;
-    step = w0 + (uint32_t)(local / tg);
-    tile = tb + (uint32_t)(local % tg);
-}
-
-template <class L, int S, int CP>
-__global__ __launch_bounds__(512) void k_batch_persistent(char *base, BatchDev b) {
-    __shared__ uint32_t sh_t, sh_abort;
-    const uint32_t total = b.nsteps * b.tiles;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            sh_t = atomicAdd(b.ticket, 1u);
-            sh_abort = __hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        const uint32_t t = sh_t;
-        const bool abort = sh_abort != 0;
-        __syncthreads();
-        if (t >= total || abort) break;
-        uint32_t s, k;
-        ticket_item(b, t, s, k);
-        const uint32_t d = b.tile_dom[k];
-        const DomDev &dd = b.doms[d];
-        if (threadIdx.x == 0 && s > 0) {
-            // bounded wait: about 2^20 polls (well under a second); every 256
-            // polls also look at the launch-wide abort flag so that one
-            // timed-out wait stops every work-group quickly
-            const uint32_t need = s * dd.ntiles;
-            uint32_t spins = 0;
-            while (__hip_atomic_load(b.done + d, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                __builtin_amdgcn_s_sleep(2);
-                ++spins;
-                if ((spins & 255u) == 0 &&
-                    __hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    sh_abort = 1;
+// Grid-wide barrier number `round` (0-based) of a launch with `nblocks`
+// work-groups.  Returns false if the launch must stop.
+__device__ __forceinline__ bool grid_barrier(const BatchDev &b, uint32_t round, uint32_t nblocks, uint32_t *sh_abort) {
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's stores have reached the L2
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(b.arrive, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (round + 1) * nblocks;
+        const uint64_t t0 = clock64();
+        uint32_t polls = 0;
+        while (__hip_atomic_load(b.arrive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if ((++polls & 63u) == 0) {
+                if (__hip_atomic_load(b.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                    *sh_abort = 1;
                     break;
                 }
-                if (spins > (1u << 20)) {
+                if (clock64() - t0 > (1ull << 31)) {   // ~1 s of shader clock
                     __hip_atomic_store(b.status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    sh_abort = 1;
+                    *sh_abort = 1;
                     break;
                 }
             }
         }
-        __syncthreads();
-        if (sh_abort) break;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // every wave sees the finished step
-        tile_dispatch<L, S, CP>(base, dd, b.tile_cell[k] + threadIdx.x, ((b.parity0 + s) & 1u) != 0);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // every wave's stores are visible device-wide
-        __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_fetch_add(b.done + d, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return *sh_abort == 0;
+}
+
+template <class L, int S, int CP>
+__global__ __launch_bounds__(512) void k_batch_persistent(char *base, BatchDev b) {
+    __shared__ uint32_t sh_abort;
+    if (threadIdx.x == 0) sh_abort = 0;
+    __syncthreads();
+    const uint32_t G = gridDim.x;
+    uint32_t round = 0;
+    for (uint32_t w0 = 0; w0 < b.nsteps; w0 += b.window) {
+        const uint32_t W = min(b.window, b.nsteps - w0);
+        for (uint32_t g = 0; g < b.ngroups; g++) {
+            const GroupDev grp = uniform_load(b.groups + g);
+            const uint32_t tb = grp.tile_begin, te = grp.tile_end;
+            for (uint32_t s = w0; s < w0 + W; s++) {
+                const bool odd = ((b.parity0 + s) & 1u) != 0;
+                for (uint32_t t = tb + blockIdx.x; t < te; t += G) {
+                    const DomDev dd = uniform_load(b.doms + uniform_u32(b.tile_dom + t));
+                    tile_dispatch<L, S, CP>(base, dd, uniform_u32(b.tile_cell + t) + threadIdx.x, odd);
+                }
+                if (!grid_barrier(b, round++, G, &sh_abort)) return;
+            }
+        }
     }
 }
 
