@@ -38,14 +38,20 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def bytes_per_cell(Q, npop, storage):
     return 2 * Q * npop * (4 if storage == "f32" else 2)
 
 
 def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, warmup, tune_cache):
+    log(f"D{D}Q{Q} {dims} {storage}: init")
     lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage)
     lat.init_fields(*fields)
     tile = lat.autotune(cache_path=tune_cache)
+    log(f"D{D}Q{Q} {dims} {storage}: tile {tile}, timing {steps} steps")
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -126,6 +132,7 @@ def main():
     N = 4096
     D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
     fields = workloads.waves_noise_2d(N)
+    log("stream ceiling")
     ceiling = esb.stream_ceiling(N * N, 10)
 
     main_run = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), "f32", fields, args.steps, args.warmup, tune_cache)
@@ -198,6 +205,7 @@ def main():
         res = {}
         for mode, name in ((0, "persistent_graph"), (1, "graph_per_step"), (2, "per_domain_loop")):
             n = args.batch_steps if mode != 2 else max(20, args.batch_steps // 5)
+            log(f"batch {len(doms)} domains, {cells} cells: mode {name}, {n} steps")
             bt.step(n, mode)          # warm-up (captures the graph)
             torch.cuda.synchronize()
             ms = bt.step_timed(n, mode)
@@ -214,6 +222,7 @@ def main():
         out["variants"] = var
 
     if not args.no_cpu:
+        log("cpu baseline (FP64 oracle on the host)")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
