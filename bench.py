@@ -88,6 +88,58 @@ def measured_traffic(bytes_per_launch):
     return d.get("hbm_bytes_per_launch")
 
 
+def _counter_rows(d):
+    import csv
+    import glob
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, counter, match):
+    """Sum of `counter` (KiB) per dispatch of kernels whose name contains all
+    of `match`."""
+    out = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter or not all(m in r.get("Kernel_Name", "") for m in match):
+            continue
+        k = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        out[k] = out.get(k, 0.0) + float(r["Counter_Value"])
+    return list(out.values())
+
+
+def ingest_counters(fetch_dir, write_dir, ncell=4096 * 4096):
+    """Turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
+    WRITE_SIZE, KiB per dispatch) into HBM bytes per launch of the odd FP32
+    D2Q37 step kernel, each counter scaled by what it reads for the
+    arithmetic-free stream kernel of known size (74 FP32 planes read and
+    written once), and store them with the kernel source hash."""
+    fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
+    ref = ("k_stream_rw",)
+    known = 74 * ncell * 4
+    sf = np.median(_per_dispatch(fr, "FETCH_SIZE", ref)) * 1024 / known
+    sw = np.median(_per_dispatch(wr, "WRITE_SIZE", ref)) * 1024 / known
+    step = ("k_step", "LatD2Q37", "Li0ELb1ELb1")          # FP32 storage, odd layout, two populations
+    f = np.median(_per_dispatch(fr, "FETCH_SIZE", step)) * 1024
+    w = np.median(_per_dispatch(wr, "WRITE_SIZE", step)) * 1024
+    bpl = bytes_per_cell(37, 2, "f32") * ncell
+    res = {"kernel": "k_step<D2Q37, FP32, odd layout, f+g>", "grid": [4096, 4096],
+           "fetch_bytes_raw": f, "write_bytes_raw": w, "stream_kernel_fetch_factor": sf,
+           "stream_kernel_write_factor": sw, "hbm_bytes_per_launch": f / sf + w / sw,
+           "algorithmic_bytes_per_launch": bpl, "traffic_over_algorithmic": (f / sf + w / sw) / bpl,
+           "kernel_source_hash": kernel_source_hash(),
+           "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -- python3 bench.py --steps 6 --warmup 2 "
+                        "--no-variants --no-cpu",
+                        "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -- python3 bench.py --steps 6 --warmup 2 "
+                        "--no-variants --no-cpu",
+                        f"python bench.py --ingest-counters {fetch_dir} {write_dir}"]}
+    with open(PROFILE_TRAFFIC, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(json.dumps(res, indent=1))
+
+
 def cpu_baseline(seconds=12.0):
     """The FP64 oracle on the host: D2Q37, N_f = 3, 1024^2 periodic, same
     initial recipe, as many whole steps as fit in about `seconds`."""
@@ -118,7 +170,12 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only (the batched and single-domain paths have no "
               "multi-GPU mode); run with --gpus 1", file=sys.stderr)
