@@ -89,21 +89,33 @@ def measured_traffic(bytes_per_launch):
 
 
 def _counter_rows(d):
+    """Counter records of every rocprofv3 output under directory d: the
+    SQLite (rocpd) databases rocprofv3 writes by default, or CSV files."""
     import csv
     import glob
+    import sqlite3
     rows = []
+    for path in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
+        db = sqlite3.connect(path)
+        for name, counter, value, disp, grid in db.execute(
+                "select kernel_name, counter_name, value, dispatch_id, grid_size from counters_collection"):
+            rows.append({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value,
+                         "Dispatch_Id": f"{path}:{disp}", "Grid_Size": grid})
+        db.close()
     for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         with open(path) as fh:
             rows.extend(csv.DictReader(fh))
     return rows
 
 
-def _per_dispatch(rows, counter, match):
+def _per_dispatch(rows, counter, match, grid=None):
     """Sum of `counter` (KiB) per dispatch of kernels whose name contains all
-    of `match`."""
+    of `match` (and, if given, whose grid has `grid` work-items)."""
     out = {}
     for r in rows:
         if r.get("Counter_Name") != counter or not all(m in r.get("Kernel_Name", "") for m in match):
+            continue
+        if grid is not None and int(r.get("Grid_Size", grid)) != grid:
             continue
         k = r.get("Dispatch_Id") or r.get("Correlation_Id")
         out[k] = out.get(k, 0.0) + float(r["Counter_Value"])
@@ -121,14 +133,18 @@ def ingest_counters(fetch_dir, write_dir, ncell=4096 * 4096):
     known = 74 * ncell * 4
     sf = np.median(_per_dispatch(fr, "FETCH_SIZE", ref)) * 1024 / known
     sw = np.median(_per_dispatch(wr, "WRITE_SIZE", ref)) * 1024 / known
-    step = ("k_step", "LatD2Q37", "Li0ELb1ELb1")          # FP32 storage, odd layout, two populations
-    f = np.median(_per_dispatch(fr, "FETCH_SIZE", step)) * 1024
-    w = np.median(_per_dispatch(wr, "WRITE_SIZE", step)) * 1024
+    step = ("k_step<esbgk::LatD2Q37, 0, true, true,",)     # FP32 storage, odd layout, two populations
+    f = np.median(_per_dispatch(fr, "FETCH_SIZE", step, ncell)) * 1024
+    w = np.median(_per_dispatch(wr, "WRITE_SIZE", step, ncell)) * 1024
+    step_e = ("k_step<esbgk::LatD2Q37, 0, false, true,",)  # even layout
+    fe = np.median(_per_dispatch(fr, "FETCH_SIZE", step_e, ncell)) * 1024
+    we = np.median(_per_dispatch(wr, "WRITE_SIZE", step_e, ncell)) * 1024
     bpl = bytes_per_cell(37, 2, "f32") * ncell
     res = {"kernel": "k_step<D2Q37, FP32, odd layout, f+g>", "grid": [4096, 4096],
            "fetch_bytes_raw": f, "write_bytes_raw": w, "stream_kernel_fetch_factor": sf,
            "stream_kernel_write_factor": sw, "hbm_bytes_per_launch": f / sf + w / sw,
            "algorithmic_bytes_per_launch": bpl, "traffic_over_algorithmic": (f / sf + w / sw) / bpl,
+           "even_kernel": {"hbm_bytes_per_launch": fe / sf + we / sw, "traffic_over_algorithmic": (fe / sf + we / sw) / bpl},
            "kernel_source_hash": kernel_source_hash(),
            "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -- python3 bench.py --steps 6 --warmup 2 "
                         "--no-variants --no-cpu",
@@ -220,8 +236,8 @@ def main():
                                "Pr=0.71, tau=0.6, kappa=0.2, shear+thermal waves (amplitude 1e-3) + N(0,1e-5^2) "
                                "noise seed 1611",
                    "lattice": "D2Q37", "grid": [N, N], "storage": "f32", "N_f": Nf, "Pr": Pr, "tau": tau,
-                   "tile": {"block": main_run["tile"][0], "order": main_run["tile"][1],
-                            "policy": main_run["tile"][2]},
+                   "tile": {p: dict(zip(("block", "order", "policy", "cells_per_item"), t))
+                            for p, t in zip(("even_kernel", "odd_kernel"), main_run["tile"])},
                    "algorithmic_bytes_per_cell_step": bytes_per_cell(Q, 2, "f32"),
                    "hbm_GBs_per_step_avg": round(bpl / (step_ms * 1e-3) / 1e9, 1)},
         "roofline": roof,

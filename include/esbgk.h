@@ -171,22 +171,25 @@ int esbgk_load(esbgk_t *h, const char *path);
  * NULL, n entries) the time of each.  Synchronous. */
 int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch_ms);
 
-/* Launch shape of the step kernels: block = work-group size (a multiple of
- * 64 in [64, 512]; 0 = default 256); order = work-group order over the
- * cells (0 = default = 1; 1 = dispatch order; 2 = contiguous runs of cells
- * per XCD); policy = cache policy of the population loads and stores
- * (0 = default = 1; 1 = normal; 2 = non-temporal).  ESBGK_EINVAL otherwise.
- * Results do not depend on the launch shape. */
-int esbgk_set_tile(esbgk_t *h, int block, int order, int policy);
-int esbgk_get_tile(const esbgk_t *h, int *block, int *order, int *policy);
+/* Launch shape of the step kernels.  parity: 0 = the kernel that reads the
+ * even layout, 1 = the odd-layout kernel, -1 = both.  block = work-group
+ * size (a multiple of 64 in [64, 512]; 0 = 256); order = work-group order
+ * over the cells (0 = default = 1; 1 = dispatch order; 2 = contiguous runs
+ * of cells per XCD); policy = cache policy of the population loads and
+ * stores (0 = default = 1; 1 = normal; 2 = non-temporal); cells_per_item =
+ * consecutive chunks of `block` cells one work-group sweeps (1..64; 0 = 1).
+ * ESBGK_EINVAL otherwise.  Results do not depend on the launch shape. */
+int esbgk_set_tile(esbgk_t *h, int parity, int block, int order, int policy, int cells_per_item);
+int esbgk_get_tile(const esbgk_t *h, int parity, int *block, int *order, int *policy, int *cells_per_item);
 
-/* Autotune the launch shape: if cache_path names a file holding an entry
- * for this lattice, N_f class, storage and size class, apply it; otherwise
- * time every candidate (block 128/256/512 x both orders x both policies,
- * an even number of steps each) on the handle's own state, restore that
- * state bitwise, apply the fastest and append it to cache_path (if not
- * NULL).  budget_ms bounds the timing (<= 0: no bound).  Needs a second copy
- * of the population storage on the device while it runs.  Synchronous. */
+/* Autotune the launch shape of each parity: if cache_path names a file
+ * holding entries for this lattice, N_f class, storage and size class, apply
+ * them; otherwise time every candidate (block 128/256/512 x both orders x
+ * both policies x 1/4/16 chunks per work-group; each launch timed alone) on
+ * the handle's own state, restore that state bitwise, apply the fastest
+ * shape per parity and append both to cache_path (if not NULL).  budget_ms
+ * bounds the timing (<= 0: no bound).  Needs a second copy of the
+ * population storage on the device while it runs.  Synchronous. */
 int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
 
 /* Measured ceiling of the step kernels' memory pattern: an in-place read and

@@ -70,8 +70,8 @@ _sig("esbgk_write_populations", [_vp, _dp, _dp])
 _sig("esbgk_save", [_vp, ctypes.c_char_p])
 _sig("esbgk_load", [_vp, ctypes.c_char_p])
 _sig("esbgk_step_timed", [_vp, ctypes.c_int64, _dp, _dp])
-_sig("esbgk_set_tile", [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int])
-_sig("esbgk_get_tile", [_vp, _ip, _ip, _ip])
+_sig("esbgk_set_tile", [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int])
+_sig("esbgk_get_tile", [_vp, ctypes.c_int, _ip, _ip, _ip, _ip])
 _sig("esbgk_autotune", [_vp, ctypes.c_double, ctypes.c_char_p])
 _sig("esbgk_destroy", [_vp], None)
 _sig("esbgk_stream_ceiling", [ctypes.c_int64, ctypes.c_int, _dp])
@@ -239,13 +239,18 @@ class Lattice:
         _check(_lib.esbgk_step_timed(self._h, int(n), ctypes.byref(tot), _p(per)))
         return tot.value, per
 
-    def set_tile(self, block: int = 0, order: int = 0, policy: int = 0):
-        _check(_lib.esbgk_set_tile(self._h, block, order, policy))
+    def set_tile(self, block: int = 0, order: int = 0, policy: int = 0, cells_per_item: int = 0, parity: int = -1):
+        _check(_lib.esbgk_set_tile(self._h, parity, block, order, policy, cells_per_item))
 
-    def get_tile(self):
-        b, o, p = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        _check(_lib.esbgk_get_tile(self._h, ctypes.byref(b), ctypes.byref(o), ctypes.byref(p)))
-        return b.value, o.value, p.value
+    def get_tile(self, parity: int | None = None):
+        """(block, order, policy, cells_per_item) of one parity's kernel, or
+        a pair (even, odd) when parity is None."""
+        if parity is None:
+            return self.get_tile(0), self.get_tile(1)
+        b, o, p, k = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(_lib.esbgk_get_tile(self._h, parity, ctypes.byref(b), ctypes.byref(o), ctypes.byref(p),
+                                   ctypes.byref(k)))
+        return b.value, o.value, p.value, k.value
 
     def autotune(self, budget_ms: float = 0.0, cache_path: str | None = None):
         """Pick (and optionally cache) the fastest launch shape; returns it."""

@@ -152,12 +152,15 @@ int all_inited(const esbgk_batch_t *b) {
 // Enqueue the work of n steps in the given mode onto b->stream (no graph).
 void enqueue(esbgk_batch_t *b, int64_t n, int mode, uint32_t grid) {
     if (mode == 2) {
+        Tile t;
+        t.block = b->block;
+        t.policy = b->policy;
         for (int64_t s = 0; s < n; s++) {
             const bool odd = ((b->steps + s) & 1) != 0;
             for (int k = 0; k < b->n; k++)
                 b->ops->step(b->fb(k), b->gb(k), (uint32_t)b->su[k].plane_bytes,
                              (uint32_t)(b->su[k].plane_bytes * b->Q), b->su[k].geom, b->su[k].coll, odd,
-                             b->su[k].npop == 2, b->block, 0, b->policy, b->stream);
+                             b->su[k].npop == 2, t, b->stream);
         }
     } else if (mode == 1) {
         for (int64_t s = 0; s < n; s++)

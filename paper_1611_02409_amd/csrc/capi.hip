@@ -236,11 +236,15 @@ struct esbgk_lattice {
     hipStream_t stream = nullptr;
     int64_t steps = 0;
     bool initialized = false;
-    int block = 256, remap = 0, policy = 0;
+    Tile tile[2];   // launch shape of the even- and odd-layout step kernels
     double *d_partials = nullptr;
     double *d_totals = nullptr;
     uint32_t nchunks = 0;
 
+    void launch_step() {
+        ops->step(fb(), gb(), pb(), sb(), su.geom, su.coll, odd(), has_g(), tile[odd() ? 1 : 0], stream);
+        steps++;
+    }
     char *fb() const { return buf; }
     char *gb() const { return su.npop == 2 ? buf + su.bytes / 2 : nullptr; }
     uint32_t pb() const { return (uint32_t)su.plane_bytes; }
@@ -460,11 +464,7 @@ int esbgk_step(esbgk_t *h, int64_t n) {
         set_error("n must be >= 0");
         return ESBGK_EINVAL;
     }
-    for (int64_t k = 0; k < n; k++) {
-        h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(), h->block,
-                     h->remap, h->policy, h->stream);
-        h->steps++;
-    }
+    for (int64_t k = 0; k < n; k++) h->launch_step();
     return launch_error();
 }
 
@@ -746,9 +746,7 @@ int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch
     int rc = ESBGK_OK;
     ESBGK_HIP(hipEventRecord(ev[0], h->stream));
     for (int64_t k = 0; k < n; k++) {
-        h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(), h->block,
-                     h->remap, h->policy, h->stream);
-        h->steps++;
+        h->launch_step();
         ESBGK_HIP(hipEventRecord(ev[k + 1], h->stream));
     }
     rc = launch_error();
@@ -765,30 +763,42 @@ int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch
     return rc;
 }
 
-int esbgk_set_tile(esbgk_t *h, int block, int order, int policy) {
+int esbgk_set_tile(esbgk_t *h, int parity, int block, int order, int policy, int cells_per_item) {
     clear_error();
     if (int rc = check(h)) return rc;
     if (block == 0) block = 256;
+    if (cells_per_item == 0) cells_per_item = 1;
     if (block < 64 || block > 512 || (block & 63)) {
         set_error("block must be a multiple of 64 in [64, 512] (got %d)", block);
         return ESBGK_EINVAL;
     }
-    if (order < 0 || order > 2 || policy < 0 || policy > 2) {
-        set_error("order and policy must be 0, 1 or 2 (got %d, %d)", order, policy);
+    if (parity < -1 || parity > 1 || order < 0 || order > 2 || policy < 0 || policy > 2 || cells_per_item < 1 ||
+        cells_per_item > 64) {
+        set_error("need parity -1..1, order and policy 0..2, cells_per_item 1..64");
         return ESBGK_EINVAL;
     }
-    h->block = block;
-    h->remap = order == 2 ? 1 : 0;
-    h->policy = policy == 2 ? 1 : 0;
+    Tile t;
+    t.block = block;
+    t.remap = order == 2 ? 1 : 0;
+    t.policy = policy == 2 ? 1 : 0;
+    t.cpi = cells_per_item;
+    if (parity != 1) h->tile[0] = t;
+    if (parity != 0) h->tile[1] = t;
     return ESBGK_OK;
 }
 
-int esbgk_get_tile(const esbgk_t *h, int *block, int *order, int *policy) {
+int esbgk_get_tile(const esbgk_t *h, int parity, int *block, int *order, int *policy, int *cells_per_item) {
     clear_error();
     if (int rc = check(h)) return rc;
-    if (block) *block = h->block;
-    if (order) *order = h->remap ? 2 : 1;
-    if (policy) *policy = h->policy ? 2 : 1;
+    if (parity < 0 || parity > 1) {
+        set_error("parity must be 0 (even-layout kernel) or 1 (odd-layout kernel)");
+        return ESBGK_EINVAL;
+    }
+    const Tile &t = h->tile[parity];
+    if (block) *block = t.block;
+    if (order) *order = t.remap ? 2 : 1;
+    if (policy) *policy = t.policy ? 2 : 1;
+    if (cells_per_item) *cells_per_item = t.cpi;
     return ESBGK_OK;
 }
 
@@ -809,72 +819,81 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
     if (cache_path) {
         std::ifstream in(cache_path);
         std::string line;
+        bool got[2] = {false, false};
         while (std::getline(in, line)) {
             if (line.rfind(key + " ", 0) != 0) continue;
-            int b, o, p;
-            if (sscanf(line.c_str() + key.size(), " block %d order %d policy %d", &b, &o, &p) == 3)
-                return esbgk_set_tile(h, b, o, p);
+            int par, b, o, p, k;
+            if (sscanf(line.c_str() + key.size(), " parity %d block %d order %d policy %d cpi %d", &par, &b, &o, &p,
+                       &k) == 5 &&
+                (par == 0 || par == 1) && esbgk_set_tile(h, par, b, o, p, k) == ESBGK_OK)
+                got[par] = true;
         }
+        if (got[0] && got[1]) return ESBGK_OK;
     }
     DevTmp save;
     ESBGK_HIP(hipMalloc(&save.p, h->su.bytes));
     ESBGK_HIP(hipMemcpyAsync(save.p, h->buf, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
     const int64_t steps0 = h->steps;
-    hipEvent_t e0, e1;
-    ESBGK_HIP(hipEventCreate(&e0));
-    ESBGK_HIP(hipEventCreate(&e1));
-    double best = 1e30;
-    int bb = h->block, bo = h->remap ? 2 : 1, bp = h->policy ? 2 : 1;
+    hipEvent_t ev[7];
+    for (auto &e : ev) ESBGK_HIP(hipEventCreate(&e));
+    double best[2] = {1e30, 1e30};
+    Tile bestt[2] = {h->tile[0], h->tile[1]};
     const auto t_start = std::chrono::steady_clock::now();
     int rc = ESBGK_OK;
     for (int block : {256, 512, 128})
-        for (int order : {1, 2})
-            for (int policy : {1, 2}) {
-                const double el =
-                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
-                if (rc || (budget_ms > 0 && el > budget_ms && best < 1e30)) continue;
-                esbgk_set_tile(h, block, order, policy);
-                for (int k = 0; k < 2; k++) {   // warm-up pair
-                    h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(),
-                                 h->block, h->remap, h->policy, h->stream);
-                    h->steps++;
-                }
-                // best of three timings of six steps (an even count keeps the parity)
-                for (int rep = 0; rep < 3; rep++) {
-                    (void)hipEventRecord(e0, h->stream);
-                    for (int k = 0; k < 6; k++) {
-                        h->ops->step(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(),
-                                     h->has_g(), h->block, h->remap, h->policy, h->stream);
-                        h->steps++;
+        for (int remap : {0, 1})
+            for (int policy : {0, 1})
+                for (int cpi : {1, 4, 16}) {
+                    const double el =
+                        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+                    if (rc || (budget_ms > 0 && el > budget_ms && best[1] < 1e30)) continue;
+                    Tile t;
+                    t.block = block;
+                    t.remap = remap;
+                    t.policy = policy;
+                    t.cpi = cpi;
+                    h->tile[0] = h->tile[1] = t;
+                    h->launch_step();   // warm-up pair
+                    h->launch_step();
+                    for (int rep = 0; rep < 2; rep++) {
+                        // six launches, each bracketed by events: three per parity
+                        int par_of[6];
+                        (void)hipEventRecord(ev[0], h->stream);
+                        for (int k = 0; k < 6; k++) {
+                            par_of[k] = h->odd() ? 1 : 0;
+                            h->launch_step();
+                            (void)hipEventRecord(ev[k + 1], h->stream);
+                        }
+                        if ((rc = launch_error())) break;
+                        (void)hipEventSynchronize(ev[6]);
+                        for (int k = 0; k < 6; k++) {
+                            float ms = 0;
+                            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+                            const int par = par_of[k];
+                            if (ms < best[par]) {
+                                best[par] = ms;
+                                bestt[par] = t;
+                            }
+                        }
                     }
-                    (void)hipEventRecord(e1, h->stream);
-                    if ((rc = launch_error())) break;
-                    (void)hipEventSynchronize(e1);
-                    float ms = 0;
-                    (void)hipEventElapsedTime(&ms, e0, e1);
-                    if (ms / 6 < best) {
-                        best = ms / 6;
-                        bb = block;
-                        bo = order;
-                        bp = policy;
-                    }
                 }
-                if (rc) break;
-            }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto &e : ev) (void)hipEventDestroy(e);
     ESBGK_HIP(hipMemcpyAsync(h->buf, save.p, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->steps = steps0;
     if (rc) return rc;
-    esbgk_set_tile(h, bb, bo, bp);
+    h->tile[0] = bestt[0];
+    h->tile[1] = bestt[1];
     if (cache_path) {
         FILE *fp = std::fopen(cache_path, "a");
         if (!fp) {
             set_error("cannot append to %s", cache_path);
             return ESBGK_EIO;
         }
-        std::fprintf(fp, "%s block %d order %d policy %d ms_per_step %.4f\n", key.c_str(), bb, bo, bp, best);
+        for (int par = 0; par < 2; par++)
+            std::fprintf(fp, "%s parity %d block %d order %d policy %d cpi %d ms %.4f\n", key.c_str(), par,
+                         bestt[par].block, bestt[par].remap ? 2 : 1, bestt[par].policy ? 2 : 1, bestt[par].cpi,
+                         best[par]);
         std::fclose(fp);
     }
     return ESBGK_OK;

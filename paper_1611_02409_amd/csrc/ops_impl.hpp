@@ -8,20 +8,26 @@
 namespace esbgk {
 
 // ---------------------------------------------------------------- step
+// One work-group sweeps cpi consecutive chunks of blockDim.x cells, so the
+// cache lines that straddle two chunks (the odd layout reads and writes
+// x +- c) are reused from its own CU's caches.
 template <class L, int S, bool ODD, bool HAS_G, int CP>
 __global__ __launch_bounds__(512) void k_step(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
-                                              uint32_t remap) {
+                                              uint32_t remap, uint32_t cpi) {
     const uint32_t blk = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    const uint32_t cell = blk * blockDim.x + threadIdx.x;
-    if (cell >= g.ncell) return;
-    Nbr<L, S> nb;
-    if constexpr (ODD) nb.init(cell, g);
-    else nb.own = cell * StoreBytes<S>::value;
     const Sets R(fb, gb, pb, sb);
-    float F[L::Q], E[HAS_G ? L::Q : 1];
-    gather<L, S, ODD, HAS_G, CP>(R, nb, F, E);
-    collide<L, HAS_G>(cp, F, E);
-    scatter<L, S, ODD, HAS_G, CP>(R, nb, F, E);
+    const uint32_t first = blk * blockDim.x * cpi + threadIdx.x;
+    for (uint32_t k = 0; k < cpi; k++) {
+        const uint32_t cell = first + k * blockDim.x;
+        if (cell >= g.ncell) return;
+        Nbr<L, S> nb;
+        if constexpr (ODD) nb.init(cell, g);
+        else nb.own = cell * StoreBytes<S>::value;
+        float F[L::Q], E[HAS_G ? L::Q : 1];
+        gather<L, S, ODD, HAS_G, CP>(R, nb, F, E);
+        collide<L, HAS_G>(cp, F, E);
+        scatter<L, S, ODD, HAS_G, CP>(R, nb, F, E);
+    }
 }
 
 // ---------------------------------------------------------------- init
@@ -173,21 +179,22 @@ template <class L, int S>
 struct OpsImpl {
     template <int CP>
     static void step_cp(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd,
-                        bool has_g, int block, int remap, hipStream_t s) {
-        const uint32_t nb = nblocks(g.ncell, block);
+                        bool has_g, int block, int remap, int cpi, hipStream_t s) {
+        const uint32_t nb = nblocks(g.ncell, block * cpi);
+        const uint32_t k = (uint32_t)cpi;
         if (odd) {
-            if (has_g) k_step<L, S, true, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
-            else k_step<L, S, true, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            if (has_g) k_step<L, S, true, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
+            else k_step<L, S, true, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
         } else {
-            if (has_g) k_step<L, S, false, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
-            else k_step<L, S, false, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap);
+            if (has_g) k_step<L, S, false, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
+            else k_step<L, S, false, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
         }
     }
     // policy 0: default caching; 1: non-temporal loads and stores
     static void step(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd,
-                     bool has_g, int block, int remap, int policy, hipStream_t s) {
-        if (policy) step_cp<2>(fb, gb, pb, sb, g, c, odd, has_g, block, remap, s);
-        else step_cp<0>(fb, gb, pb, sb, g, c, odd, has_g, block, remap, s);
+                     bool has_g, const Tile &t, hipStream_t s) {
+        if (t.policy) step_cp<2>(fb, gb, pb, sb, g, c, odd, has_g, t.block, t.remap, t.cpi, s);
+        else step_cp<0>(fb, gb, pb, sb, g, c, odd, has_g, t.block, t.remap, t.cpi, s);
     }
     static void init(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
                      hipStream_t s) {

@@ -51,10 +51,18 @@ Coll make_coll(const LatticeConsts &lc, const double prm[4], int D, int Nf, doub
 // out = [rho - 1 | u (D planes) | T - 1], each ncell floats.
 int fields_to_dev(const double *rho, const double *u, const double *T, int D, uint64_t ncell, float *out);
 
+// Launch shape of one step kernel.
+struct Tile {
+    int block = 256;   // work-group size
+    int remap = 0;     // 1: contiguous cell runs per XCD
+    int policy = 0;    // 1: non-temporal population loads and stores
+    int cpi = 1;       // chunks of `block` cells per work-group
+};
+
 // Kernel dispatch of one (lattice, storage) combination.
 struct Ops {
     void (*step)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
-                 int block, int remap, int policy, hipStream_t s);
+                 const Tile &t, hipStream_t s);
     void (*init)(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
                  hipStream_t s);
     void (*moments)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, float *out,

@@ -215,3 +215,40 @@ def test_write_populations_roundtrip():
     fg, _ = lat.read_populations()
     fo2, _ = sim.get_pops()
     assert pop_error(li["w"], fg, fo2[perm]) < 3e-6
+
+
+@pytest.mark.parametrize("tiles", [
+    [(-1, 64, 1, 1, 1)],
+    [(-1, 512, 2, 2, 16)],
+    [(0, 256, 1, 2, 4), (1, 128, 2, 1, 3)],
+    [(0, 512, 2, 1, 64), (1, 256, 1, 2, 1)],
+])
+def test_launch_shape_does_not_change_results(tiles):
+    """Work-group size, order, cache policy and chunks per work-group, set
+    per parity, leave every population bitwise unchanged (ragged grid, so
+    partial chunks and partial work-groups are exercised)."""
+    dims = (77, 53)
+    fields = workloads.random_state(dims, seed=21)
+    ref = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 5)
+    lat = esb.Lattice(2, 37, 3, 0.71, 0.6, dims)
+    for par, block, order, policy, cpi in tiles:
+        lat.set_tile(block, order, policy, cpi, parity=par)
+    lat.init_fields(*fields)
+    lat.step(5)
+    a, b = ref.read_populations(), lat.read_populations()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_autotune_restores_state(tmp_path):
+    dims = (96, 80)
+    fields = workloads.random_state(dims, seed=22)
+    lat = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 3)
+    before = lat.read_populations()
+    cache = str(tmp_path / "tune.txt")
+    even, odd = lat.autotune(cache_path=cache)
+    assert lat.steps == 3
+    after = lat.read_populations()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    # a second handle picks the cached shapes without timing
+    lat2 = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 0)
+    assert lat2.autotune(cache_path=cache) == (even, odd)
