@@ -30,3 +30,14 @@ def read_table(name):
             else:
                 rows.append((int(parts[0]), int(parts[1]), int(parts[2]), float(parts[3])))
     return r, rows
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_threads():
+    """The oracle runs on small grids in the tests: one thread avoids OpenMP
+    synchronisation costs that dominate at these sizes."""
+    import oracle
+    prev = oracle.set_threads(0)
+    oracle.set_threads(1)
+    yield
+    oracle.set_threads(prev)

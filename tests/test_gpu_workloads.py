@@ -1,0 +1,104 @@
+"""Workload-level GPU parity against the FP64 oracle.
+
+* 3D: D3Q39 thermal Taylor-Green vortex at 32^3 (u0 = 0.02, T wave 1e-2,
+  N_f = 2, Pr = 0.71, tau = 0.7): kinetic energy history and final fields.
+* 4096^2 D2Q37 waves + noise (N_f = 3, Pr = 0.71, tau = 0.6) after 1000 and
+  5000 steps against the stored oracle reference (8x8 block means on a 512^2
+  grid), for FP32, FP16- and BF16-deviation storage: relative L2 of rho, u,
+  T, and the drift of total mass and energy.  Bounds: FP32 1e-5 (the FP32
+  target); FP16/BF16: measured values with a factor-2 margin, stated in the
+  assertion messages and in the design notes.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+
+import oracle  # noqa: E402
+import workloads  # noqa: E402
+from gpu_helpers import rel_l2  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+esb = pytest.importorskip("paper_1611_02409_amd")
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def kinetic_energy(m):
+    return 0.5 * float(np.sum(m["rho"] * (m["u"] ** 2).sum(0)))
+
+
+def test_taylor_green_32_kinetic_energy_history():
+    n, steps, every = 32, 240, 40
+    fields = workloads.taylor_green_3d(n)
+    lat = esb.Lattice(3, 39, 2, 0.71, 0.7, (n, n, n))
+    lat.init_fields(*fields)
+    prev = oracle.set_threads(0)
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    try:
+        sim = oracle.Sim(3, 39, 2, 0.71, 0.7, (n, n, n))
+        sim.init(*fields)
+        k0 = kinetic_energy(sim.moments())
+        for t in range(every, steps + 1, every):
+            lat.step(every)
+            sim.step(every)
+            mg, mo = lat.read_moments(), sim.moments()
+            kg, ko = kinetic_energy(mg), kinetic_energy(mo)
+            print(f"TGV 32^3 step {t}: KE/KE0 gpu {kg / k0:.6e} oracle {ko / k0:.6e}")
+            assert abs(kg - ko) / ko < 1e-5
+        assert ko / k0 > 1e-3          # still well resolved
+        for key in ("rho", "u", "T"):
+            assert rel_l2(mg[key], mo[key]) < 1e-5
+    finally:
+        oracle.set_threads(prev)
+
+
+def _reference(n=4096, Pr=0.71):
+    path = os.path.join(GOLDEN, f"ref_waves{n}_pr{Pr:g}.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"reference {os.path.basename(path)} not generated (tests/golden/make_references.py)")
+    return np.load(path)
+
+
+BOUNDS = {  # relative L2 of (rho, u, T) and relative drift of mass and energy
+    "f32": (1e-5, 1e-5, 1e-5, 1e-9),
+    "f16": (2e-6, 2e-3, 2e-6, 1e-7),
+    "bf16": (2e-5, 2e-2, 2e-5, 1e-6),
+}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("n,steps", [(4096, 1000), (4096, 5000), (1024, 5000)])
+def test_waves_against_fp64_reference(storage, n, steps):
+    ref = _reference(n)
+    if f"rho_{steps}" not in ref.files:
+        pytest.skip(f"reference has no snapshot at step {steps}")
+    fields = workloads.waves_noise_2d(n)
+    lat = esb.Lattice(2, 37, 3, 0.71, float(ref["tau"]), (n, n), storage=storage)
+    lat.init_fields(*fields)
+    t0 = lat.totals()
+    lat.step(steps)
+    t1 = lat.totals()
+    m = lat.read_moments()
+    bm = lambda a: workloads.block_mean(a, int(ref["out_n"]))
+    rho_r = 1.0 + ref[f"rho_{steps}"].astype(np.float64)
+    T_r = 1.0 + ref[f"T_{steps}"].astype(np.float64)
+    u_r = np.stack([ref[f"ux_{steps}"], ref[f"uy_{steps}"]]).astype(np.float64)
+    e_rho = rel_l2(1.0 + bm(m["rho"] - 1.0), rho_r)
+    e_T = rel_l2(1.0 + bm(m["T"] - 1.0), T_r)
+    e_u = rel_l2(np.stack([bm(m["u"][0]), bm(m["u"][1])]), u_r)
+    to = ref[f"totals_{steps}"]
+    d_mass = abs(t1[0] - t0[0]) / t0[0]
+    d_en = abs(t1[-1] - t0[-1]) / t0[-1]
+    print(f"{storage} {n}^2 x {steps}: rho {e_rho:.2e} u {e_u:.2e} T {e_T:.2e} | mass drift {d_mass:.2e} "
+          f"energy drift {d_en:.2e} | gpu-oracle totals {(t1 - to) / to[0]}")
+    b = BOUNDS[storage]
+    assert e_rho < b[0] and e_u < b[1] and e_T < b[2], (storage, e_rho, e_u, e_T, b)
+    assert d_mass < b[3] and d_en < b[3], (storage, d_mass, d_en, b[3])
