@@ -201,7 +201,7 @@ def main():
     import paper_1611_02409_amd as esb
     import workloads
 
-    tune_cache = os.path.join(ROOT, "profiles", "autotune_cache.txt")
+    tune_cache = None   # tune afresh each run (about a second per workload)
     N = 4096
     D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
     fields = workloads.waves_noise_2d(N)
