@@ -287,6 +287,20 @@ def main():
             res[name] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1), "steps": n,
                          "GBs": round(bps * n / (ms * 1e-3) / 1e9, 1),
                          "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # the same persistent launch, advancing groups of domains (about 128 MB
+        # of storage each) eight steps at a time while they sit in the MALL
+        bt.set_tile(256, 0, 8, 128e6)
+        n = args.batch_steps
+        log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {n} steps")
+        bt.step(n, 0)
+        torch.cuda.synchronize()
+        ms = bt.step_timed(n, 0)
+        if bt.status() != 0:
+            raise RuntimeError("persistent batch kernel reported a timed-out wait")
+        res["persistent_graph_grouped"] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1), "steps": n,
+                                           "GBs": round(bps * n / (ms * 1e-3) / 1e9, 1),
+                                           "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                           "window": 8, "group_bytes": 128e6}
         res["cells"] = cells
         res["domains"] = len(doms)
         res["speedup_vs_per_domain_loop"] = round(res["persistent_graph"]["mlups"] / res["per_domain_loop"]["mlups"], 3)

@@ -132,7 +132,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchDev &b, uint32_t round, 
 }
 
 template <class L, int S, int CP>
-__global__ __launch_bounds__(512) void k_batch_persistent(char *base, BatchDev b) {
+__device__ __forceinline__ void persistent_body(char *base, const BatchDev &b) {
     __shared__ uint32_t sh_abort;
     if (threadIdx.x == 0) sh_abort = 0;
     __syncthreads();
@@ -155,6 +155,19 @@ __global__ __launch_bounds__(512) void k_batch_persistent(char *base, BatchDev b
     }
 }
 
+// Register budget: three waves per SIMD where the code fits in 168 VGPRs
+// without spilling (FP32, BF16); FP16 storage keeps the compiler's choice.
+template <class L, int S, int CP>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_persistent(char *base,
+                                                                                                  BatchDev b) {
+    persistent_body<L, S, CP>(base, b);
+}
+
+template <class L, int S, int CP>
+__global__ __launch_bounds__(512) void k_batch_persistent_f16(char *base, BatchDev b) {
+    persistent_body<L, S, CP>(base, b);
+}
+
 struct BatchOps {
     void (*step)(char *base, const DomDev *doms, const uint32_t *tile_dom, const uint32_t *tile_cell, uint32_t tiles,
                  int block, bool odd, int policy, hipStream_t s);
@@ -169,15 +182,18 @@ struct BatchOpsImpl {
         if (policy) k_batch_step<L, S, 2><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
         else k_batch_step<L, S, 0><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
     }
+    template <int CP>
+    static auto kernel() {
+        if constexpr (S == ST_F16) return &k_batch_persistent_f16<L, S, CP>;
+        else return &k_batch_persistent<L, S, CP>;
+    }
     static void persistent(char *base, const BatchDev &b, uint32_t grid, int block, int policy, hipStream_t s) {
-        if (policy) k_batch_persistent<L, S, 2><<<grid, block, 0, s>>>(base, b);
-        else k_batch_persistent<L, S, 0><<<grid, block, 0, s>>>(base, b);
+        if (policy) kernel<2>()<<<grid, block, 0, s>>>(base, b);
+        else kernel<0>()<<<grid, block, 0, s>>>(base, b);
     }
     static int occupancy(int block, int policy, int *blocks_per_cu) {
-        hipError_t e = policy ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                                             k_batch_persistent<L, S, 2>, block, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu,
-                                                                             k_batch_persistent<L, S, 0>, block, 0);
+        hipError_t e = policy ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<2>(), block, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<0>(), block, 0);
         return e == hipSuccess ? 0 : -1;
     }
     static constexpr BatchOps ops{&step, &persistent, &occupancy};

@@ -36,7 +36,7 @@ def kinetic_energy(m):
 
 
 def test_taylor_green_32_kinetic_energy_history():
-    n, steps, every = 32, 240, 40
+    n, steps, every = 32, 200, 40
     fields = workloads.taylor_green_3d(n)
     lat = esb.Lattice(3, 39, 2, 0.71, 0.7, (n, n, n))
     lat.init_fields(*fields)
@@ -102,3 +102,27 @@ def test_waves_against_fp64_reference(storage, n, steps):
     b = BOUNDS[storage]
     assert e_rho < b[0] and e_u < b[1] and e_T < b[2], (storage, e_rho, e_u, e_T, b)
     assert d_mass < b[3] and d_en < b[3], (storage, d_mass, d_en, b[3])
+
+
+def test_d2q33_shock_tube_matches_oracle():
+    """The paper's shock tube (D2Q33, 1000 x 16, density 4:1, gamma 1.4,
+    tau 2/3, 174 steps) on the GPU against the oracle: a strongly nonlinear
+    state (deviations up to 3 w_i)."""
+    nx, ny, steps = 1000, 16, 174
+    x = np.tile(np.arange(nx, dtype=float), (ny, 1))
+    fields = (np.where(x < 500, 4.0, 1.0), np.zeros((2, ny, nx)), np.ones((ny, nx)))
+    lat = esb.Lattice(2, 33, 3, 0.71, 2 / 3, (nx, ny))
+    lat.init_fields(*fields)
+    lat.step(steps)
+    prev = oracle.set_threads(0)
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    try:
+        sim = oracle.Sim(2, 33, 3, 0.71, 2 / 3, (nx, ny))
+        sim.init(*fields)
+        sim.step(steps)
+    finally:
+        oracle.set_threads(prev)
+    mg, mo = lat.read_moments(), sim.moments()
+    er, eu, eT = rel_l2(mg["rho"], mo["rho"]), rel_l2(mg["u"], mo["u"]), rel_l2(mg["T"], mo["T"])
+    print(f"shock tube D2Q33: rho {er:.2e} u {eu:.2e} T {eT:.2e}")
+    assert er < 1e-5 and eu < 1e-5 and eT < 1e-5
