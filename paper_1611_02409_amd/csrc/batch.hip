@@ -16,7 +16,7 @@ const BatchOps *batch_ops_d3q39(int storage);
 // Zero the launch's counters (a plain kernel, so the reset can live inside a
 // captured graph).
 static __global__ void k_batch_reset(uint32_t *ctr) {
-    if (threadIdx.x < 2) ctr[threadIdx.x] = 0;
+    if (threadIdx.x < 3) ctr[threadIdx.x] = 0;
 }
 
 static const BatchOps *get_batch_ops(int D, int Q, int storage) {
@@ -50,7 +50,7 @@ struct esbgk_batch {
     DomDev *d_doms = nullptr;
     uint32_t *d_tile_dom = nullptr, *d_tile_cell = nullptr;
     GroupDev *d_groups = nullptr;
-    uint32_t *d_ctr = nullptr;   // [barrier arrivals, status]
+    uint32_t *d_ctr = nullptr;   // [barrier arrivals, status, tile tickets]
     uint32_t tiles = 0, ngroups = 0;
     int tables_block = -1;
     // captured graphs keyed by (mode, n, parity, block, policy, window)
@@ -180,6 +180,7 @@ void enqueue(esbgk_batch_t *b, int64_t n, int mode, uint32_t grid) {
         bd.parity0 = (uint32_t)(b->steps & 1);
         bd.arrive = b->d_ctr;
         bd.status = b->d_ctr + 1;
+        bd.claim = b->d_ctr + 2;
         b->bops->persistent(b->buf, bd, grid, b->block, b->policy, b->stream);
     }
 }
@@ -258,8 +259,8 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
             break;
         }
         if (hipMalloc(&b->d_doms, sizeof(DomDev) * n) != hipSuccess ||
-            hipMalloc(&b->d_ctr, sizeof(uint32_t) * 2) != hipSuccess ||
-            hipMemsetAsync(b->d_ctr, 0, sizeof(uint32_t) * 2, b->stream) != hipSuccess) {
+            hipMalloc(&b->d_ctr, sizeof(uint32_t) * 3) != hipSuccess ||
+            hipMemsetAsync(b->d_ctr, 0, sizeof(uint32_t) * 3, b->stream) != hipSuccess) {
             set_error("device allocation of batch tables failed");
             rc = ESBGK_ENOMEM;
             break;

@@ -46,6 +46,7 @@ struct BatchDev {
     uint32_t parity0;             // parity of the step count at launch
     uint32_t *arrive;             // grid-barrier arrival counter
     uint32_t *status;             // 0 ok, 1 a barrier wait timed out
+    uint32_t *claim;              // tile tickets claimed so far in this launch
 };
 
 // A record every lane of the wave reads at the same address, returned in
@@ -133,22 +134,34 @@ __device__ __forceinline__ bool grid_barrier(const BatchDev &b, uint32_t round, 
 
 template <class L, int S, int CP>
 __device__ __forceinline__ void persistent_body(char *base, const BatchDev &b) {
-    __shared__ uint32_t sh_abort;
+    __shared__ uint32_t sh_abort, sh_t;
     if (threadIdx.x == 0) sh_abort = 0;
     __syncthreads();
     const uint32_t G = gridDim.x;
     uint32_t round = 0;
+    // Tiles of a round are handed out by a launch-wide ticket counter, so a
+    // work-group that drew cheap tiles (N_f = 0 domains, partial tiles) takes
+    // more of them.  Every work-group ends a round with exactly one failing
+    // draw, so the round's last ticket is known to all: next = first + tiles + G.
+    uint32_t first = 0;
     for (uint32_t w0 = 0; w0 < b.nsteps; w0 += b.window) {
         const uint32_t W = min(b.window, b.nsteps - w0);
         for (uint32_t g = 0; g < b.ngroups; g++) {
             const GroupDev grp = uniform_load(b.groups + g);
-            const uint32_t tb = grp.tile_begin, te = grp.tile_end;
+            const uint32_t tb = grp.tile_begin, nt = grp.tile_end - grp.tile_begin;
             for (uint32_t s = w0; s < w0 + W; s++) {
                 const bool odd = ((b.parity0 + s) & 1u) != 0;
-                for (uint32_t t = tb + blockIdx.x; t < te; t += G) {
+                for (;;) {
+                    if (threadIdx.x == 0) sh_t = atomicAdd(b.claim, 1u) - first;
+                    __syncthreads();
+                    const uint32_t k = sh_t;
+                    __syncthreads();
+                    if (k >= nt) break;
+                    const uint32_t t = tb + k;
                     const DomDev dd = uniform_load(b.doms + uniform_u32(b.tile_dom + t));
                     tile_dispatch<L, S, CP>(base, dd, uniform_u32(b.tile_cell + t) + threadIdx.x, odd);
                 }
+                first += nt + G;
                 if (!grid_barrier(b, round++, G, &sh_abort)) return;
             }
         }
