@@ -3,13 +3,15 @@
 Prints one JSON line.  The headline workload is a 4096 x 4096 periodic D2Q37
 domain with both populations stored in FP32 (N_f = 3, Pr = 0.71, tau = 0.6,
 superposed shear and thermal waves plus seeded noise); a step is one fused
-stream-collide launch over the whole grid with inputs resident in HBM.
-`value` is million lattice-cell updates per second (MLUPS) over exactly
---steps timed steps.  Variants (FP16/BF16 deviation storage, the batched
-256-domain workload in its three execution modes, D3Q39 at 256^3) are
-reported beside it, each with its own HBM-roofline fraction.
+stream-collide launch over the whole grid with inputs resident in HBM, in the
+two-copy pull streaming scheme.  `value` is million lattice-cell updates per
+second (MLUPS) over exactly --steps timed steps.  Variants (the same workload
+with A-A in-place streaming, FP16/BF16 deviation storage, D3Q39 at 256^3,
+the batched 256-domain workload in its execution modes) are reported beside
+it, each with its HBM-roofline fraction.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-variants] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--variants aa,f16,bf16,d3q39,batch]
+                    [--no-variants] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -46,12 +48,12 @@ def bytes_per_cell(Q, npop, storage):
     return 2 * Q * npop * (4 if storage == "f32" else 2)
 
 
-def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, warmup, tune_cache):
-    log(f"D{D}Q{Q} {dims} {storage}: init")
-    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage)
+def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, warmup, tune_cache, streaming="pull"):
+    log(f"D{D}Q{Q} {dims} {storage} {streaming}: init")
+    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, streaming=streaming)
     lat.init_fields(*fields)
     tile = lat.autotune(cache_path=tune_cache)
-    log(f"D{D}Q{Q} {dims} {storage}: tile {tile}, timing {steps} steps")
+    log(f"D{D}Q{Q} {dims} {storage} {streaming}: tile {tile}, timing {steps} steps")
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -65,7 +67,7 @@ def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, war
     even = per[1::2] if first_odd else per[0::2]
     return dict(lat=lat, tile=tile, total_ms=total_ms, wall_s=wall, ncell=ncell,
                 mlups=ncell * steps / (total_ms * 1e-3) / 1e6, odd_ms=float(np.mean(odd)),
-                even_ms=float(np.mean(even)))
+                even_ms=float(np.mean(even)), launch_ms=float(np.mean(per)))
 
 
 def roofline(bytes_per_launch, launch_ms, peak=HBM_PEAK_GBS, traffic=None):
@@ -74,10 +76,10 @@ def roofline(bytes_per_launch, launch_ms, peak=HBM_PEAK_GBS, traffic=None):
             "traffic": traffic}
 
 
-def measured_traffic(bytes_per_launch):
-    """HBM bytes per launch of the odd step kernel from the committed
-    rocprofv3 counter summary, if it was taken from the current kernel
-    source; otherwise None."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of one FP32 D2Q37 4096^2 step kernel ("pull",
+    "aa_even" or "aa_odd") from the committed rocprofv3 counter summary, if it
+    was taken from the current kernel source; otherwise None."""
     try:
         with open(PROFILE_TRAFFIC) as fh:
             d = json.load(fh)
@@ -85,7 +87,7 @@ def measured_traffic(bytes_per_launch):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
 
 
 def _counter_rows(d):
@@ -122,10 +124,16 @@ def _per_dispatch(rows, counter, match, grid=None):
     return list(out.values())
 
 
+# demangled-name prefixes of the FP32 (storage 0) D2Q37 step kernels with
+# both populations, by layout (0 A-A even, 1 A-A odd, 2 pull)
+STEP_KERNELS = {"pull": "k_step<esbgk::LatD2Q37, 0, 2, true,", "aa_even": "k_step<esbgk::LatD2Q37, 0, 0, true,",
+                "aa_odd": "k_step<esbgk::LatD2Q37, 0, 1, true,"}
+
+
 def ingest_counters(fetch_dir, write_dir, ncell=4096 * 4096):
     """Turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
-    WRITE_SIZE, KiB per dispatch) into HBM bytes per launch of the odd FP32
-    D2Q37 step kernel, each counter scaled by what it reads for the
+    WRITE_SIZE, KiB per dispatch) into HBM bytes per launch of the FP32
+    D2Q37 step kernels, each counter scaled by what it reads for the
     arithmetic-free stream kernel of known size (74 FP32 planes read and
     written once), and store them with the kernel source hash."""
     fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
@@ -133,23 +141,24 @@ def ingest_counters(fetch_dir, write_dir, ncell=4096 * 4096):
     known = 74 * ncell * 4
     sf = np.median(_per_dispatch(fr, "FETCH_SIZE", ref)) * 1024 / known
     sw = np.median(_per_dispatch(wr, "WRITE_SIZE", ref)) * 1024 / known
-    step = ("k_step<esbgk::LatD2Q37, 0, true, true,",)     # FP32 storage, odd layout, two populations
-    f = np.median(_per_dispatch(fr, "FETCH_SIZE", step, ncell)) * 1024
-    w = np.median(_per_dispatch(wr, "WRITE_SIZE", step, ncell)) * 1024
-    step_e = ("k_step<esbgk::LatD2Q37, 0, false, true,",)  # even layout
-    fe = np.median(_per_dispatch(fr, "FETCH_SIZE", step_e, ncell)) * 1024
-    we = np.median(_per_dispatch(wr, "WRITE_SIZE", step_e, ncell)) * 1024
     bpl = bytes_per_cell(37, 2, "f32") * ncell
-    res = {"kernel": "k_step<D2Q37, FP32, odd layout, f+g>", "grid": [4096, 4096],
-           "fetch_bytes_raw": f, "write_bytes_raw": w, "stream_kernel_fetch_factor": sf,
-           "stream_kernel_write_factor": sw, "hbm_bytes_per_launch": f / sf + w / sw,
-           "algorithmic_bytes_per_launch": bpl, "traffic_over_algorithmic": (f / sf + w / sw) / bpl,
-           "even_kernel": {"hbm_bytes_per_launch": fe / sf + we / sw, "traffic_over_algorithmic": (fe / sf + we / sw) / bpl},
+    kernels = {}
+    for name, prefix in STEP_KERNELS.items():
+        fd = _per_dispatch(fr, "FETCH_SIZE", (prefix,), ncell)
+        wd = _per_dispatch(wr, "WRITE_SIZE", (prefix,), ncell)
+        if not fd or not wd:
+            continue
+        f, w = np.median(fd) * 1024, np.median(wd) * 1024
+        kernels[name] = {"fetch_bytes_raw": f, "write_bytes_raw": w, "dispatches": [len(fd), len(wd)],
+                         "hbm_bytes_per_launch": f / sf + w / sw,
+                         "traffic_over_algorithmic": (f / sf + w / sw) / bpl}
+    res = {"workload": "D2Q37 4096x4096 FP32 f+g", "algorithmic_bytes_per_launch": bpl,
+           "stream_kernel_fetch_factor": sf, "stream_kernel_write_factor": sw, "kernels": kernels,
            "kernel_source_hash": kernel_source_hash(),
            "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -- python3 bench.py --steps 6 --warmup 2 "
-                        "--no-variants --no-cpu",
+                        "--variants aa --no-cpu",
                         "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -- python3 bench.py --steps 6 --warmup 2 "
-                        "--no-variants --no-cpu",
+                        "--variants aa --no-cpu",
                         f"python bench.py --ingest-counters {fetch_dir} {write_dir}"]}
     with open(PROFILE_TRAFFIC, "w") as fh:
         json.dump(res, fh, indent=1)
@@ -178,11 +187,16 @@ def cpu_baseline(seconds=12.0):
             "sample": f"FP64 oracle, D2Q37 1024x1024 periodic, N_f=3, Pr=0.71, tau=0.6, {steps} steps in {el:.1f} s"}
 
 
+VARIANTS = ("aa", "f16", "bf16", "d3q39", "batch")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--variants", default=",".join(VARIANTS),
+                    help="comma list of variants to time beside the headline: " + ",".join(VARIANTS))
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=200)
@@ -196,6 +210,10 @@ def main():
         print("bench.py: this build runs on one GPU only (the batched and single-domain paths have no "
               "multi-GPU mode); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    variants = set() if args.no_variants else {v for v in args.variants.split(",") if v}
+    unknown = variants - set(VARIANTS)
+    if unknown:
+        ap.error(f"unknown variants {sorted(unknown)}")
 
     import torch
     import paper_1611_02409_amd as esb
@@ -205,19 +223,14 @@ def main():
     N = 4096
     D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
     fields = workloads.waves_noise_2d(N)
-    log("stream ceiling")
-    ceiling = esb.stream_ceiling(N * N, 10)
-
-    main_run = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), "f32", fields, args.steps, args.warmup, tune_cache)
     bpl = bytes_per_cell(Q, 2, "f32") * N * N
-    roof = roofline(bpl, main_run["odd_ms"], traffic=measured_traffic(bpl))
-    roof["kernel"] = "k_step<D2Q37, FP32, odd layout> (the slower of the two A-A kernels)"
+
+    # headline: two-copy pull streaming, FP32
+    main_run = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), "f32", fields, args.steps, args.warmup, tune_cache)
+    roof = roofline(bpl, main_run["launch_ms"], traffic=measured_traffic("pull"))
+    roof["kernel"] = "k_step<D2Q37, FP32, pull layout> (the one kernel of every step)"
     roof["bytes_per_launch"] = bpl
-    roof["avg_launch_ms"] = round(main_run["odd_ms"], 4)
-    roof["even_kernel"] = {"avg_launch_ms": round(main_run["even_ms"], 4),
-                           "achieved": round(bpl / (main_run["even_ms"] * 1e-3) / 1e9, 1)}
-    roof["measured_stream_ceiling_GBs"] = round(ceiling, 1)
-    roof["frac_of_measured_ceiling"] = round(bpl / (main_run["odd_ms"] * 1e-3) / 1e9 / ceiling, 4)
+    roof["avg_launch_ms"] = round(main_run["launch_ms"], 4)
     step_ms = main_run["total_ms"] / args.steps
     out = {
         "metric": METRIC,
@@ -236,8 +249,9 @@ def main():
                                "Pr=0.71, tau=0.6, kappa=0.2, shear+thermal waves (amplitude 1e-3) + N(0,1e-5^2) "
                                "noise seed 1611",
                    "lattice": "D2Q37", "grid": [N, N], "storage": "f32", "N_f": Nf, "Pr": Pr, "tau": tau,
+                   "streaming": "two-copy pull (reads x - c_i, aligned writes; bitwise equal to A-A in place)",
                    "tile": {p: dict(zip(("block", "order", "policy", "cells_per_item"), t))
-                            for p, t in zip(("even_kernel", "odd_kernel"), main_run["tile"])},
+                            for p, t in zip(("even_step", "odd_step"), main_run["tile"])},
                    "algorithmic_bytes_per_cell_step": bytes_per_cell(Q, 2, "f32"),
                    "hbm_GBs_per_step_avg": round(bpl / (step_ms * 1e-3) / 1e9, 1)},
         "roofline": roof,
@@ -245,73 +259,100 @@ def main():
     del main_run
     torch.cuda.empty_cache()
 
-    if not args.no_variants:
-        var = {}
-        for storage in ("f16", "bf16"):
-            r = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), storage, fields, args.steps, args.warmup, tune_cache)
-            b = bytes_per_cell(Q, 2, storage) * N * N
-            var[f"d2q37_4096_{storage}_dev"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / args.steps, 4),
-                                                "roofline_frac_odd": round(b / (r["odd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                                "GBs_per_step": round(b / (r["total_ms"] / args.steps * 1e-3) / 1e9, 1),
-                                                "tile": r["tile"]}
-            del r
-            torch.cuda.empty_cache()
-        del fields
+    var = {}
+    if "aa" in variants:
+        r = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), "f32", fields, args.steps, args.warmup, tune_cache,
+                        streaming="aa")
+        var["d2q37_4096_f32_aa_in_place"] = {
+            "mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / args.steps, 4),
+            "even_kernel": {"avg_launch_ms": round(r["even_ms"], 4),
+                            "frac_of_hbm_peak": round(bpl / (r["even_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "traffic": measured_traffic("aa_even")},
+            "odd_kernel": {"avg_launch_ms": round(r["odd_ms"], 4),
+                           "frac_of_hbm_peak": round(bpl / (r["odd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "traffic": measured_traffic("aa_odd")},
+            "tile": r["tile"]}
+        del r
+        torch.cuda.empty_cache()
+    for storage in ("f16", "bf16"):
+        if storage not in variants:
+            continue
+        r = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), storage, fields, args.steps, args.warmup, tune_cache)
+        b = bytes_per_cell(Q, 2, storage) * N * N
+        var[f"d2q37_4096_{storage}_dev"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / args.steps, 4),
+                                            "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                            "GBs_per_step": round(b / (r["total_ms"] / args.steps * 1e-3) / 1e9, 1),
+                                            "streaming": "pull", "tile": r["tile"]}
+        del r
+        torch.cuda.empty_cache()
+    del fields
+    if "d3q39" in variants:
         # D3Q39 256^3 thermal Taylor-Green vortex, FP32
         n3 = 256
         f3 = workloads.taylor_green_3d(n3)
-        r = time_single(esb, torch, 3, 39, 2, 0.71, 0.7, (n3, n3, n3), "f32", f3, max(50, args.steps // 2),
-                        args.warmup, tune_cache)
-        b = bytes_per_cell(39, 2, "f32") * n3 ** 3
         s3 = max(50, args.steps // 2)
+        r = time_single(esb, torch, 3, 39, 2, 0.71, 0.7, (n3, n3, n3), "f32", f3, s3, args.warmup, tune_cache)
+        b = bytes_per_cell(39, 2, "f32") * n3 ** 3
         var["d3q39_256cube_f32"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / s3, 4),
-                                    "roofline_frac_odd": round(b / (r["odd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                    "GBs_per_step": round(b / (r["total_ms"] / s3 * 1e-3) / 1e9, 1), "tile": r["tile"]}
+                                    "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                    "GBs_per_step": round(b / (r["total_ms"] / s3 * 1e-3) / 1e9, 1),
+                                    "streaming": "pull", "tile": r["tile"]}
         del r, f3
         torch.cuda.empty_cache()
-        # batched: 256 independent domains
-        doms = workloads.batch_domains(256)
-        bt = esb.Batch(2, 37, [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms])
-        for k, d in enumerate(doms):
-            bt.init_fields(k, *workloads.batch_fields(d))
-        cells, bps = bt.info()
-        res = {}
-        for mode, name in ((0, "persistent_graph"), (1, "graph_per_step"), (2, "per_domain_loop")):
-            n = args.batch_steps if mode != 2 else max(20, args.batch_steps // 5)
-            log(f"batch {len(doms)} domains, {cells} cells: mode {name}, {n} steps")
-            bt.step(n, mode)          # warm-up (captures the graph)
-            torch.cuda.synchronize()
-            ms = bt.step_timed(n, mode)
-            if bt.status() != 0:
-                raise RuntimeError("persistent batch kernel reported a timed-out wait")
-            res[name] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1), "steps": n,
-                         "GBs": round(bps * n / (ms * 1e-3) / 1e9, 1),
-                         "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        # the same persistent launch, advancing groups of domains (about 128 MB
-        # of storage each) eight steps at a time while they sit in the MALL
-        bt.set_tile(256, 0, 8, 128e6)
-        n = args.batch_steps
-        log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {n} steps")
-        bt.step(n, 0)
-        torch.cuda.synchronize()
-        ms = bt.step_timed(n, 0)
-        if bt.status() != 0:
-            raise RuntimeError("persistent batch kernel reported a timed-out wait")
-        res["persistent_graph_grouped"] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1), "steps": n,
-                                           "GBs": round(bps * n / (ms * 1e-3) / 1e9, 1),
-                                           "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                           "window": 8, "group_bytes": 128e6}
-        res["cells"] = cells
-        res["domains"] = len(doms)
-        res["speedup_vs_per_domain_loop"] = round(res["persistent_graph"]["mlups"] / res["per_domain_loop"]["mlups"], 3)
-        var["batched_256_d2q37_f32"] = res
-        del bt
+    if "batch" in variants:
+        var["batched_256_d2q37_f32"] = time_batch(esb, torch, workloads, args.batch_steps)
+        torch.cuda.empty_cache()
+    if var:
         out["variants"] = var
+
+    # the arithmetic-free copy kernel of the same pattern, last: its buffer is
+    # allocated and freed outside the timed lattices
+    log("stream ceiling")
+    ceiling = esb.stream_ceiling(N * N, 10)
+    roof["measured_stream_ceiling_GBs"] = round(ceiling, 1)
+    roof["frac_of_measured_ceiling"] = round(roof["achieved"] / ceiling, 4)
 
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle on the host)")
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
+
+
+def time_batch(esb, torch, workloads, batch_steps):
+    """256 independent domains (A-A in place) in the three execution modes,
+    plus the persistent launch advancing MALL-sized domain groups."""
+    doms = workloads.batch_domains(256)
+    bt = esb.Batch(2, 37, [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms])
+    for k, d in enumerate(doms):
+        bt.init_fields(k, *workloads.batch_fields(d))
+    cells, bps = bt.info()
+    res = {}
+
+    def run(name, mode, n):
+        bt.step(n, mode)          # warm-up (captures the graph)
+        torch.cuda.synchronize()
+        ms = bt.step_timed(n, mode)
+        if bt.status() != 0:
+            raise RuntimeError("persistent batch kernel reported a timed-out wait")
+        res[name] = {"mlups": round(cells * n / (ms * 1e-3) / 1e6, 1), "steps": n,
+                     "GBs": round(bps * n / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+    for mode, name in ((0, "persistent_graph"), (1, "graph_per_step"), (2, "per_domain_loop")):
+        n = batch_steps if mode != 2 else max(20, batch_steps // 5)
+        log(f"batch {len(doms)} domains, {cells} cells: mode {name}, {n} steps")
+        run(name, mode, n)
+    # the same persistent launch, advancing groups of domains (about 128 MB
+    # of storage each) eight steps at a time while they sit in the MALL
+    bt.set_tile(256, 0, 8, 128e6)
+    log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {batch_steps} steps")
+    run("persistent_graph_grouped", 0, batch_steps)
+    res["persistent_graph_grouped"].update(window=8, group_bytes=128e6)
+    res["cells"] = cells
+    res["domains"] = len(doms)
+    res["speedup_vs_per_domain_loop"] = round(res["persistent_graph"]["mlups"] / res["per_domain_loop"]["mlups"], 3)
+    del bt
+    return res
 
 
 if __name__ == "__main__":

@@ -41,7 +41,8 @@
  *   Storage: ESBGK_F32 keeps each population as an FP32 deviation from its
  *     rest-state value; ESBGK_F16_DEV and ESBGK_BF16_DEV keep it as an FP16 or
  *     BF16 deviation multiplied by a per-direction power of two near 1/w_i.
- *     Collision arithmetic is FP32 in all modes.
+ *     Collision arithmetic is FP32 in all modes.  ESBGK_PULL or-ed into the
+ *     storage argument selects the two-copy streaming scheme.
  *   Errors: every int-returning call returns ESBGK_OK (0) or a negative code
  *     below and sets a thread-local message (esbgk_last_error).  No call
  *     throws or aborts.  A failing call leaves the handle usable unless it
@@ -72,6 +73,17 @@ extern "C" {
 #define ESBGK_F32 0
 #define ESBGK_F16_DEV 1
 #define ESBGK_BF16_DEV 2
+
+/* Streaming scheme, or-ed into a storage argument (single-domain handles).
+ * Without it the populations are one copy updated in place with the A-A
+ * pattern: even steps read and write each cell's own slots (writing f_i
+ * into slot opp(i)), odd steps read slot opp(i) at x - c_i and write slot i
+ * at x + c_i.  With ESBGK_PULL the library keeps two copies: every step
+ * reads slot i at x - c_i from the current copy and writes slot i at x of
+ * the other one, so every store covers whole aligned cache lines.  Twice
+ * the storage; the arithmetic and the results are bit for bit those of
+ * A-A. */
+#define ESBGK_PULL 0x10
 
 typedef struct esbgk_lattice esbgk_t;
 typedef struct esbgk_batch esbgk_batch_t;

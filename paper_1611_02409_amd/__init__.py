@@ -31,6 +31,16 @@ _vp = ctypes.c_void_p
 
 F32, F16_DEV, BF16_DEV = 0, 1, 2
 STORAGE = {"f32": F32, "f16": F16_DEV, "bf16": BF16_DEV}
+PULL = 0x10   # two-copy pull streaming (or-ed into the storage code)
+STREAMING = {"aa": 0, "pull": PULL}
+
+
+def _storage_code(storage: str, streaming: str = "aa") -> int:
+    if storage not in STORAGE:
+        raise ValueError(f"storage must be one of {sorted(STORAGE)}")
+    if streaming not in STREAMING:
+        raise ValueError(f"streaming must be one of {sorted(STREAMING)}")
+    return STORAGE[storage] | STREAMING[streaming]
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EDEVICE", -5: "ESTATE", -6: "ENONFINITE", -7: "EIO"}
 
 
@@ -128,32 +138,35 @@ def _dims(dims):
     return (ctypes.c_int64 * 3)(*(list(dims) + [1] * (3 - len(dims))))
 
 
-def storage_bytes(D, Q, Nf, dims, storage="f32") -> int:
+def storage_bytes(D, Q, Nf, dims, storage="f32", streaming="aa") -> int:
     out = ctypes.c_size_t()
-    _check(_lib.esbgk_storage_bytes(D, Q, Nf, _dims(dims), STORAGE[storage], ctypes.byref(out)))
+    _check(_lib.esbgk_storage_bytes(D, Q, Nf, _dims(dims), _storage_code(storage, streaming), ctypes.byref(out)))
     return out.value
 
 
 class Lattice:
     """One periodic domain.  Fields use numpy shape (ny, nx) / (nz, ny, nx),
-    velocity (D, ...)."""
+    velocity (D, ...).  streaming: "aa" (one copy, A-A in place) or "pull"
+    (two copies, aligned stores; same results bit for bit)."""
 
     def __init__(self, D: int, Q: int, Nf: int, Pr: float, tau: float, dims, storage: str = "f32",
-                 kappa: float = 0.2, device: int = 0, stream=None):
+                 kappa: float = 0.2, device: int = 0, stream=None, streaming: str = "aa"):
         self.D, self.Q, self.Nf, self.Pr, self.tau = D, Q, Nf, Pr, tau
         self.dims = tuple(int(d) for d in dims)
         if len(self.dims) != D:
             raise ValueError("dims must have D entries")
         self.storage = storage
+        self.streaming = streaming
+        code = _storage_code(storage, streaming)
         self.ncell = int(np.prod(self.dims))
         self.shape = tuple(reversed(self.dims))
         self._h = None
-        nbytes = storage_bytes(D, Q, Nf, self.dims, storage)
+        nbytes = storage_bytes(D, Q, Nf, self.dims, storage, streaming)
         self.device = torch.device("cuda", device)
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = _vp()
-        _check(_lib.esbgk_create_ex(D, Q, Nf, Pr, tau, _dims(self.dims), STORAGE[storage], self._buf.data_ptr(),
+        _check(_lib.esbgk_create_ex(D, Q, Nf, Pr, tau, _dims(self.dims), code, self._buf.data_ptr(),
                                     nbytes, self._stream.cuda_stream, ctypes.byref(h)))
         self._h = h
         if kappa != 0.2:

@@ -158,9 +158,9 @@ void enqueue(esbgk_batch_t *b, int64_t n, int mode, uint32_t grid) {
         for (int64_t s = 0; s < n; s++) {
             const bool odd = ((b->steps + s) & 1) != 0;
             for (int k = 0; k < b->n; k++)
-                b->ops->step(b->fb(k), b->gb(k), (uint32_t)b->su[k].plane_bytes,
-                             (uint32_t)(b->su[k].plane_bytes * b->Q), b->su[k].geom, b->su[k].coll, odd,
-                             b->su[k].npop == 2, t, b->stream);
+                b->ops->step(b->fb(k), b->gb(k), b->fb(k), b->gb(k), (uint32_t)b->su[k].plane_bytes,
+                             (uint32_t)(b->su[k].plane_bytes * b->Q), b->su[k].geom, b->su[k].coll,
+                             odd ? LAY_ODD : LAY_EVEN, b->su[k].npop == 2, t, b->stream);
         }
     } else if (mode == 1) {
         for (int64_t s = 0; s < n; s++)
@@ -209,6 +209,10 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
         return ESBGK_EINVAL;
     }
     *out = nullptr;
+    if (storage & ESBGK_PULL) {
+        set_error("the batched path keeps the A-A in-place layout (ESBGK_PULL is for single-domain handles)");
+        return ESBGK_EUNSUPPORTED;
+    }
     auto *b = new (std::nothrow) esbgk_batch();
     if (!b) {
         set_error("host allocation failed");
@@ -305,8 +309,8 @@ int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const do
     ESBGK_HIP(hipMalloc(&tmp, host.size() * sizeof(float)));
     hipError_t e = hipMemcpyAsync(tmp, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) {
-        b->ops->init(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * b->Q), s.geom.ncell,
-                     s.coll, (const float *)tmp, s.npop == 2, b->stream);
+        b->ops->init(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * b->Q), s.geom, s.coll,
+                     (const float *)tmp, LAY_EVEN, s.npop == 2, b->stream);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     }
@@ -458,7 +462,7 @@ int esbgk_batch_read_moments(esbgk_batch_t *b, int k, double *rho, double *u, do
     float *tmp = nullptr;
     ESBGK_HIP(hipMalloc(&tmp, planes * n * sizeof(float)));
     b->ops->moments(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * b->Q), s.geom, s.coll,
-                    (b->steps & 1) != 0, s.npop == 2, tmp, P != nullptr, b->stream);
+                    (b->steps & 1) ? LAY_ODD : LAY_EVEN, s.npop == 2, tmp, P != nullptr, b->stream);
     std::vector<float> host(planes * n);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
@@ -527,7 +531,7 @@ int esbgk_batch_read_populations(esbgk_batch_t *b, int k, double *f, double *g) 
     float *tmp = nullptr;
     ESBGK_HIP(hipMalloc(&tmp, n * Q * npop * sizeof(float)));
     b->ops->cells(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * Q), s.geom, s.coll,
-                  (b->steps & 1) != 0, npop == 2, nullptr, (uint32_t)n, tmp, b->stream);
+                  (b->steps & 1) ? LAY_ODD : LAY_EVEN, npop == 2, nullptr, (uint32_t)n, tmp, b->stream);
     std::vector<float> host(n * Q * npop);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)

@@ -42,6 +42,8 @@ FastDiv make_fastdiv(uint32_t d) {
     return f;
 }
 
+// storage: the codec part of a storage argument (ESBGK_F32, ESBGK_F16_DEV or
+// ESBGK_BF16_DEV)
 const Ops *get_ops(int D, int Q, int storage) {
     if (storage < 0 || storage > 2) return nullptr;
     if (D == 2 && Q == 37) return ops_d2q37(storage);
@@ -78,10 +80,13 @@ int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, cons
         set_error("dims is NULL");
         return ESBGK_EINVAL;
     }
-    if (storage < 0 || storage > 2) {
+    const int codec = storage & ~ESBGK_PULL;
+    if (codec < 0 || codec > 2) {
         set_error("unknown storage mode %d", storage);
         return ESBGK_EINVAL;
     }
+    out.codec = codec;
+    out.copies = (storage & ESBGK_PULL) ? 2 : 1;
     if (!lattice_consts(D, Q, out.lc)) {
         set_error("unsupported lattice D%dQ%d (supported: D2Q37, D2Q33, D3Q39)", D, Q);
         return ESBGK_EUNSUPPORTED;
@@ -106,7 +111,7 @@ int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, cons
             return ESBGK_EUNSUPPORTED;
         }
     }
-    out.esize = storage == ESBGK_F32 ? 4 : 2;
+    out.esize = codec == ESBGK_F32 ? 4 : 2;
     out.plane_bytes = ncell * out.esize;
     const uint64_t set_bytes = out.plane_bytes * (uint64_t)Q;
     if (set_bytes >= ((uint64_t)1 << 32)) {
@@ -117,9 +122,10 @@ int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, cons
     }
     out.npop = Nf > 0 ? 2 : 1;
     // planes are 256-byte aligned inside a set only through the cell count;
-    // sets start 256-byte aligned
-    const uint64_t set_stride = (set_bytes + 255) & ~uint64_t(255);
-    out.bytes = set_stride * out.npop;
+    // sets and copies start 256-byte aligned
+    out.set_stride = (set_bytes + 255) & ~uint64_t(255);
+    out.copy_bytes = out.set_stride * out.npop;
+    out.bytes = out.copy_bytes * out.copies;
     out.coll = make_coll(out.lc, out.prm, D, Nf, kappa);
     Geom &g = out.geom;
     g.nx = (uint32_t)nd[0];
@@ -170,7 +176,7 @@ struct TotConsts {
 
 // One block: sum the per-chunk plane partials in a fixed order, then weight
 // each plane by its velocity: mass = sum d, momentum = r sum c d (sign flipped
-// in the odd layout, where plane i holds direction opp(i)), energy =
+// in the A-A odd layout, where plane i holds direction opp(i)), energy =
 // sum r^2 |c|^2 d / 2 + sum g_d, plus the rest-state contributions.
 __global__ __launch_bounds__(256) void k_totals_final(const double *partials, uint32_t nchunks, TotConsts tc,
                                                       double *out) {
@@ -203,13 +209,13 @@ __global__ __launch_bounds__(256) void k_totals_final(const double *partials, ui
     }
 }
 
-void launch_totals_final(const double *partials, uint32_t nchunks, const LatticeConsts &lc, int npop, bool odd,
+void launch_totals_final(const double *partials, uint32_t nchunks, const LatticeConsts &lc, int npop, bool opp_planes,
                          uint64_t ncell, double hN, double *out, hipStream_t s) {
     TotConsts tc{};
     tc.Q = lc.Q;
     tc.D = lc.D;
     tc.npop = npop;
-    tc.odd = odd ? 1 : 0;
+    tc.odd = opp_planes ? 1 : 0;
     for (int i = 0; i < lc.Q; i++) {
         for (int a = 0; a < 3; a++) tc.c[i][a] = lc.c[i][a];
         tc.isc[i] = std::ldexp(1.0, -lc.scale_exp[lc.shell_of[i]]);
@@ -242,14 +248,21 @@ struct esbgk_lattice {
     uint32_t nchunks = 0;
 
     void launch_step() {
-        ops->step(fb(), gb(), pb(), sb(), su.geom, su.coll, odd(), has_g(), tile[odd() ? 1 : 0], stream);
+        ops->step(fb(), gb(), wfb(), wgb(), pb(), sb(), su.geom, su.coll, lay(), has_g(), tile[odd() ? 1 : 0],
+                  stream);
         steps++;
     }
-    char *fb() const { return buf; }
-    char *gb() const { return su.npop == 2 ? buf + su.bytes / 2 : nullptr; }
+    // storage of the current state and of the state a step writes (the same
+    // storage for A-A; the other copy for two-copy pull)
+    char *copy(int64_t s) const { return buf + (su.copies == 2 ? (uint64_t)(s & 1) * su.copy_bytes : 0); }
+    char *fb() const { return copy(steps); }
+    char *gb() const { return su.npop == 2 ? fb() + su.set_stride : nullptr; }
+    char *wfb() const { return copy(steps + 1); }
+    char *wgb() const { return su.npop == 2 ? wfb() + su.set_stride : nullptr; }
     uint32_t pb() const { return (uint32_t)su.plane_bytes; }
     uint32_t sb() const { return (uint32_t)(su.plane_bytes * (uint64_t)Q); }
     bool odd() const { return (steps & 1) != 0; }
+    int lay() const { return su.copies == 2 ? LAY_PULL : odd() ? LAY_ODD : LAY_EVEN; }
     bool has_g() const { return su.npop == 2; }
 };
 
@@ -287,7 +300,7 @@ int create_impl(int D, int Q, int Nf, double Pr, double tau, const int64_t *dims
     h->Pr = Pr;
     h->tau = tau;
     for (int d = 0; d < D; d++) h->dims[d] = dims[d];
-    h->ops = get_ops(D, Q, storage);
+    h->ops = get_ops(D, Q, h->su.codec);
     h->stream = (hipStream_t)stream;
     if (external) {
         if (!dev_buf || bytes < h->su.bytes || ((uintptr_t)dev_buf & 255)) {
@@ -448,11 +461,11 @@ int esbgk_init_fields(esbgk_t *h, const double *rho, const double *u, const doub
     DevTmp tmp;
     ESBGK_HIP(hipMalloc(&tmp.p, host.size() * sizeof(float)));
     ESBGK_HIP(hipMemcpyAsync(tmp.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
-    h->ops->init(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom.ncell, h->su.coll, (const float *)tmp.p, h->has_g(),
-                 h->stream);
+    h->steps = 0;
+    h->ops->init(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, (const float *)tmp.p, h->lay(),
+                 h->has_g(), h->stream);
     if (int rc = launch_error()) return rc;
     ESBGK_HIP(hipStreamSynchronize(h->stream));
-    h->steps = 0;
     h->initialized = true;
     return ESBGK_OK;
 }
@@ -487,7 +500,7 @@ int esbgk_read_moments(esbgk_t *h, double *rho, double *u, double *T, double *P)
     const uint64_t planes = 2 + D + (P ? np : 0);
     DevTmp tmp;
     ESBGK_HIP(hipMalloc(&tmp.p, planes * n * sizeof(float)));
-    h->ops->moments(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(),
+    h->ops->moments(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->lay(), h->has_g(),
                     (float *)tmp.p, P != nullptr, h->stream);
     if (int rc = launch_error()) return rc;
     std::vector<float> host(planes * n);
@@ -517,8 +530,8 @@ int esbgk_totals(esbgk_t *h, double *out) {
     }
     h->ops->plane_sums(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom.ncell, h->Q, h->has_g(), h->d_partials,
                        h->nchunks, h->stream);
-    launch_totals_final(h->d_partials, h->nchunks, h->su.lc, h->su.npop, h->odd(), h->su.geom.ncell, 0.5 * h->Nf,
-                        h->d_totals, h->stream);
+    launch_totals_final(h->d_partials, h->nchunks, h->su.lc, h->su.npop, h->lay() == LAY_ODD, h->su.geom.ncell,
+                        0.5 * h->Nf, h->d_totals, h->stream);
     if (int rc = launch_error()) return rc;
     ESBGK_HIP(hipMemcpyAsync(out, h->d_totals, sizeof(double) * (2 + h->D), hipMemcpyDeviceToHost, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
@@ -550,7 +563,7 @@ int esbgk_read_cells(esbgk_t *h, int64_t n, const int64_t *cells, double *f, dou
     ESBGK_HIP(hipMalloc(&dl.p, n * sizeof(uint32_t)));
     ESBGK_HIP(hipMalloc(&dout.p, (size_t)n * Q * npop * sizeof(float)));
     ESBGK_HIP(hipMemcpyAsync(dl.p, list.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice, h->stream));
-    h->ops->cells(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(),
+    h->ops->cells(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->lay(), h->has_g(),
                   (const uint32_t *)dl.p, (uint32_t)n, (float *)dout.p, h->stream);
     if (int rc = launch_error()) return rc;
     std::vector<float> host((size_t)n * Q * npop);
@@ -577,7 +590,7 @@ int esbgk_read_populations(esbgk_t *h, double *f, double *g) {
     const int Q = h->Q, npop = h->su.npop;
     DevTmp dout;
     ESBGK_HIP(hipMalloc(&dout.p, n * Q * npop * sizeof(float)));
-    h->ops->cells(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->odd(), h->has_g(), nullptr,
+    h->ops->cells(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->lay(), h->has_g(), nullptr,
                   (uint32_t)n, (float *)dout.p, h->stream);
     if (int rc = launch_error()) return rc;
     std::vector<float> host(n * Q * npop);
@@ -620,7 +633,7 @@ int esbgk_write_populations(esbgk_t *h, const double *f, const double *g) {
     DevTmp din;
     ESBGK_HIP(hipMalloc(&din.p, host.size() * sizeof(float)));
     ESBGK_HIP(hipMemcpyAsync(din.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
-    h->ops->write(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->odd(), h->has_g(), (const float *)din.p,
+    h->ops->write(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->lay(), h->has_g(), (const float *)din.p,
                   h->stream);
     if (int rc = launch_error()) return rc;
     ESBGK_HIP(hipStreamSynchronize(h->stream));
@@ -649,12 +662,13 @@ int esbgk_save(esbgk_t *h, const char *path) {
     }
     std::vector<char> host;
     try {
-        host.resize(h->su.bytes);
+        host.resize(h->su.copy_bytes);
     } catch (...) {
         set_error("host allocation failed");
         return ESBGK_ENOMEM;
     }
-    ESBGK_HIP(hipMemcpyAsync(host.data(), h->buf, h->su.bytes, hipMemcpyDeviceToHost, h->stream));
+    // the current state only (one copy)
+    ESBGK_HIP(hipMemcpyAsync(host.data(), h->fb(), h->su.copy_bytes, hipMemcpyDeviceToHost, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     CkptHeader hd{};
     std::memcpy(hd.magic, "ESBGKCK1", 8);
@@ -668,7 +682,7 @@ int esbgk_save(esbgk_t *h, const char *path) {
     hd.Pr = h->Pr;
     hd.tau = h->tau;
     hd.kappa = h->kappa;
-    hd.bytes = h->su.bytes;
+    hd.bytes = h->su.copy_bytes;
     FILE *fp = std::fopen(path, "wb");
     if (!fp) {
         set_error("cannot open %s for writing", path);
@@ -701,7 +715,8 @@ int esbgk_load(esbgk_t *h, const char *path) {
         set_error("%s is not an esbgk checkpoint", path);
         return ESBGK_EIO;
     }
-    bool same = hd.D == h->D && hd.Q == h->Q && hd.Nf == h->Nf && hd.storage == h->storage && hd.bytes == h->su.bytes;
+    bool same = hd.D == h->D && hd.Q == h->Q && hd.Nf == h->Nf && hd.storage == h->storage &&
+                hd.bytes == h->su.copy_bytes;
     for (int d = 0; d < 3; d++) same = same && hd.dims[d] == h->dims[d];
     if (!same) {
         std::fclose(fp);
@@ -727,9 +742,9 @@ int esbgk_load(esbgk_t *h, const char *path) {
     h->kappa = hd.kappa;
     std::memcpy(h->su.prm, prm, sizeof prm);
     h->su.coll = make_coll(h->su.lc, prm, h->D, h->Nf, hd.kappa);
-    ESBGK_HIP(hipMemcpyAsync(h->buf, host.data(), host.size(), hipMemcpyHostToDevice, h->stream));
-    ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->steps = hd.steps;
+    ESBGK_HIP(hipMemcpyAsync(h->fb(), host.data(), host.size(), hipMemcpyHostToDevice, h->stream));
+    ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->initialized = true;
     return ESBGK_OK;
 }

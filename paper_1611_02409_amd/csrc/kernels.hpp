@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 #include "lattice.hpp"
@@ -147,6 +148,11 @@ __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t o
     if constexpr (S == ST_F32) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, (int)soff, CP);
     } else if constexpr (S == ST_F16) {
+        // round to FP32 first, then to FP16, in every kernel: otherwise the
+        // compiler may fuse the last FMA with the conversion (one rounding)
+        // in some kernels and not in others, and two paths that compute the
+        // same step would store different bits
+        asm("" : "+v"(v));
         __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)off, (int)soff, CP);
     } else {
         __builtin_amdgcn_raw_buffer_store_b16(__bfloat16_as_ushort(__float2bfloat16(v)), r, (int)off, (int)soff, CP);
@@ -164,8 +170,15 @@ struct Sets {
 
 // --------------------------------------------------------------------------
 // Neighbour offsets: wrapped coordinates of x + k for |k| <= REACH, as byte
-// offsets, so that the location x + c costs one or two adds.
+// offsets, so that the location x + c costs one or two adds.  A location is
+// a per-lane byte offset plus a wave-uniform one (added to the plane's
+// scalar offset).
 // --------------------------------------------------------------------------
+
+struct Off {
+    uint32_t v;   // per-lane byte offset
+    uint32_t s;   // wave-uniform byte offset
+};
 
 template <class L, int S>
 struct Nbr {
@@ -197,10 +210,8 @@ struct Nbr {
                 yv = yv >= int(g.ny) ? yv - int(g.ny) : yv;
             }
             xo[k + R] = uint32_t(xv) * B;
-            if constexpr (L::D == 2) {
-                yo[k + R] = uint32_t(yv) * (g.nx * B);
-            } else {
-                yo[k + R] = uint32_t(yv) * (g.nx * B);
+            yo[k + R] = uint32_t(yv) * (g.nx * B);
+            if constexpr (L::D == 3) {
                 int zv = int(z) + k;
                 if constexpr (k < 0) zv = zv < 0 ? zv + int(g.nz) : zv;
                 else if constexpr (k > 0) zv = zv >= int(g.nz) ? zv - int(g.nz) : zv;
@@ -209,73 +220,172 @@ struct Nbr {
         });
     }
 
+    __device__ __forceinline__ Off self() const { return {own, 0u}; }
+
     template <int CX, int CY, int CZ>
-    __device__ __forceinline__ uint32_t at() const {
-        if constexpr (L::D == 2) return xo[CX + R] + yo[CY + R];
-        else return xo[CX + R] + yo[CY + R] + zo[CZ + R];
+    __device__ __forceinline__ Off at() const {
+        if constexpr (L::D == 2) return {xo[CX + R] + yo[CY + R], 0u};
+        else return {xo[CX + R] + yo[CY + R] + zo[CZ + R], 0u};
+    }
+};
+
+// Row-wave addressing, for domains whose x-rows are whole waves (nx a
+// multiple of 64, waves starting at multiples of 64 cells).  y and z are the
+// same on all lanes of a wave, so their offsets are scalar.  In a wave that
+// does not touch x = 0 or x = nx - 1 ("inner"), x + k never wraps: the x
+// offset is one register plus the instruction's immediate (k + R) B.  Waves
+// at the two ends of a row wrap x per lane (RowView<.., false>).
+template <class L, int S, bool INNER>
+struct RowView {
+    static constexpr int R = L::REACH;
+    static constexpr uint32_t B = StoreBytes<S>::value;
+    uint32_t xb;                                   // (x - R) B, per lane
+    uint32_t nxB;                                  // nx B
+    uint32_t yo[2 * R + 1], zo[L::D == 3 ? 2 * R + 1 : 1];   // uniform
+
+    template <int CY, int CZ>
+    __device__ __forceinline__ uint32_t yz() const {
+        if constexpr (L::D == 2) return yo[CY + R];
+        else return yo[CY + R] + zo[CZ + R];
+    }
+    template <int CX>
+    __device__ __forceinline__ uint32_t xoff() const {
+        if constexpr (INNER || CX == 0) {
+            return xb + uint32_t((CX + R) * int(B));
+        } else {
+            const uint32_t v = xb + uint32_t((CX + R) * int(B));   // (x + CX) B, unwrapped
+            if constexpr (CX < 0) return int32_t(v) < 0 ? v + nxB : v;
+            else return v >= nxB ? v - nxB : v;
+        }
+    }
+    __device__ __forceinline__ Off self() const { return {xoff<0>(), yz<0, 0>()}; }
+    template <int CX, int CY, int CZ>
+    __device__ __forceinline__ Off at() const { return {xoff<CX>(), yz<CY, CZ>()}; }
+};
+
+template <class L, int S>
+struct RowNbr {
+    static constexpr int R = L::REACH;
+    RowView<L, S, true> v;
+    bool inner;
+
+    __device__ __forceinline__ void init(uint32_t cell, const Geom &g) {
+        constexpr uint32_t B = StoreBytes<S>::value;
+        const uint32_t c0 = __builtin_amdgcn_readfirstlane(cell);   // first cell of the wave
+        uint32_t y, z = 0, x0;
+        if constexpr (L::D == 2) {
+            y = fdiv(c0, g.by_nx);
+            x0 = c0 - y * g.nx;
+        } else {
+            z = fdiv(c0, g.by_nxy);
+            const uint32_t rem = c0 - z * (g.nx * g.ny);
+            y = fdiv(rem, g.by_nx);
+            x0 = rem - y * g.nx;
+        }
+        inner = x0 != 0 && x0 + 64 < g.nx;
+        v.xb = (cell - c0 + x0) * B - uint32_t(R) * B;
+        v.nxB = g.nx * B;
+        static_for<2 * R + 1>([&](auto kk) {
+            constexpr int k = decltype(kk)::value - R;
+            int yv = int(y) + k;
+            if constexpr (k < 0) yv = yv < 0 ? yv + int(g.ny) : yv;
+            else if constexpr (k > 0) yv = yv >= int(g.ny) ? yv - int(g.ny) : yv;
+            v.yo[k + R] = uint32_t(yv) * (g.nx * B);
+            if constexpr (L::D == 3) {
+                int zv = int(z) + k;
+                if constexpr (k < 0) zv = zv < 0 ? zv + int(g.nz) : zv;
+                else if constexpr (k > 0) zv = zv >= int(g.nz) ? zv - int(g.nz) : zv;
+                v.zo[k + R] = uint32_t(zv) * (g.nx * g.ny * B);
+            }
+        });
+    }
+    // the wrapping view; its per-lane base passes through an empty asm so that
+    // the wrapped offsets are recomputed where they are used instead of being
+    // kept alive across the collision
+    __device__ __forceinline__ RowView<L, S, false> edge() const {
+        RowView<L, S, false> e;
+        e.xb = v.xb;
+        asm volatile("" : "+v"(e.xb));
+        e.nxB = v.nxB;
+        for (int k = 0; k < 2 * R + 1; k++) e.yo[k] = v.yo[k];
+        if constexpr (L::D == 3)
+            for (int k = 0; k < 2 * R + 1; k++) e.zo[k] = v.zo[k];
+        return e;
     }
 };
 
 // --------------------------------------------------------------------------
-// Gather / scatter of all populations of one cell.
-// ODD = false: the cell's own slots (state after an even number of steps).
-// ODD = true : A-A odd layout (state after an odd number of steps).
+// Gather / scatter of all populations of one cell.  Layouts of the stored
+// state (where the value of direction i at cell x lives):
+//   LAY_EVEN: (x, plane i)             A-A, after an even number of steps
+//   LAY_ODD : (x - c_i, plane opp(i))  A-A, after an odd number of steps
+//   LAY_PULL: (x - c_i, plane i)       two-copy pull, every step; these are
+//             the post-collision values not yet streamed
 // --------------------------------------------------------------------------
 
-template <class L, int S, bool ODD, bool HAS_G, int CP = 0>
-__device__ __forceinline__ void gather(const Sets &R, const Nbr<L, S> &nb, float *F, float *E) {
-    F[0] = ld<S, CP>(R.f, nb.own, 0);
-    if constexpr (HAS_G) E[0] = ld<S, CP>(R.g, nb.own, 0);
+enum : int { LAY_EVEN = 0, LAY_ODD = 1, LAY_PULL = 2 };
+
+template <class L, int S, int LAY, bool HAS_G, int CP = 0, class NB>
+__device__ __forceinline__ void gather(const Sets &R, const NB &nb, float *F, float *E) {
+    const Off o = nb.self();
+    F[0] = ld<S, CP>(R.f, o.v, o.s);
+    if constexpr (HAS_G) E[0] = ld<S, CP>(R.g, o.v, o.s);
     static_for<L::NP>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
-        constexpr int a = 2 * p + 1, b = 2 * p + 2;
-        if constexpr (ODD) {
-            const uint32_t op = nb.template at<cx, cy, cz>();
-            const uint32_t om = nb.template at<-cx, -cy, -cz>();
-            F[a] = ld<S, CP>(R.f, om, R.so(b));
-            F[b] = ld<S, CP>(R.f, op, R.so(a));
+        constexpr int a = 2 * p + 1, b = 2 * p + 2;   // c_b = -c_a
+        if constexpr (LAY == LAY_EVEN) {
+            F[a] = ld<S, CP>(R.f, o.v, R.so(a) + o.s);
+            F[b] = ld<S, CP>(R.f, o.v, R.so(b) + o.s);
             if constexpr (HAS_G) {
-                E[a] = ld<S, CP>(R.g, om, R.so(b));
-                E[b] = ld<S, CP>(R.g, op, R.so(a));
+                E[a] = ld<S, CP>(R.g, o.v, R.so(a) + o.s);
+                E[b] = ld<S, CP>(R.g, o.v, R.so(b) + o.s);
             }
         } else {
-            F[a] = ld<S, CP>(R.f, nb.own, R.so(a));
-            F[b] = ld<S, CP>(R.f, nb.own, R.so(b));
+            // direction a comes from x - c_a, direction b from x + c_a
+            constexpr int pa = LAY == LAY_ODD ? b : a, pb = LAY == LAY_ODD ? a : b;
+            const Off op = nb.template at<cx, cy, cz>();
+            const Off om = nb.template at<-cx, -cy, -cz>();
+            F[a] = ld<S, CP>(R.f, om.v, R.so(pa) + om.s);
+            F[b] = ld<S, CP>(R.f, op.v, R.so(pb) + op.s);
             if constexpr (HAS_G) {
-                E[a] = ld<S, CP>(R.g, nb.own, R.so(a));
-                E[b] = ld<S, CP>(R.g, nb.own, R.so(b));
+                E[a] = ld<S, CP>(R.g, om.v, R.so(pa) + om.s);
+                E[b] = ld<S, CP>(R.g, op.v, R.so(pb) + op.s);
             }
         }
     });
 }
 
-// Write post-collision populations so that the layout flips parity:
-// after an even-layout read, f*_i goes to the own cell's plane opp(i); after
-// an odd-layout read, f*_i goes to (x + c_i, plane i).
-template <class L, int S, bool ODD, bool HAS_G, int CP = 0>
-__device__ __forceinline__ void scatter(const Sets &R, const Nbr<L, S> &nb, const float *F, const float *E) {
-    st<S, CP>(F[0], R.f, nb.own, 0);
-    if constexpr (HAS_G) st<S, CP>(E[0], R.g, nb.own, 0);
+// Write post-collision populations of a cell whose state was read in layout
+// LAY.  A-A flips the parity in place: after LAY_EVEN, f*_i goes to the own
+// cell's plane opp(i); after LAY_ODD, to (x + c_i, plane i).  LAY_PULL
+// writes f*_i to the own cell's plane i of the other copy (aligned, whole
+// cache lines), which is LAY_PULL again.
+template <class L, int S, int LAY, bool HAS_G, int CP = 0, class NB>
+__device__ __forceinline__ void scatter(const Sets &R, const NB &nb, const float *F, const float *E) {
+    const Off o = nb.self();
+    st<S, CP>(F[0], R.f, o.v, o.s);
+    if constexpr (HAS_G) st<S, CP>(E[0], R.g, o.v, o.s);
     static_for<L::NP>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
         constexpr int a = 2 * p + 1, b = 2 * p + 2;
-        if constexpr (ODD) {
-            const uint32_t op = nb.template at<cx, cy, cz>();
-            const uint32_t om = nb.template at<-cx, -cy, -cz>();
-            st<S, CP>(F[a], R.f, op, R.so(a));
-            st<S, CP>(F[b], R.f, om, R.so(b));
+        if constexpr (LAY == LAY_ODD) {
+            const Off op = nb.template at<cx, cy, cz>();
+            const Off om = nb.template at<-cx, -cy, -cz>();
+            st<S, CP>(F[a], R.f, op.v, R.so(a) + op.s);
+            st<S, CP>(F[b], R.f, om.v, R.so(b) + om.s);
             if constexpr (HAS_G) {
-                st<S, CP>(E[a], R.g, op, R.so(a));
-                st<S, CP>(E[b], R.g, om, R.so(b));
+                st<S, CP>(E[a], R.g, op.v, R.so(a) + op.s);
+                st<S, CP>(E[b], R.g, om.v, R.so(b) + om.s);
             }
         } else {
-            st<S, CP>(F[a], R.f, nb.own, R.so(b));
-            st<S, CP>(F[b], R.f, nb.own, R.so(a));
+            constexpr int pa = LAY == LAY_EVEN ? b : a, pb = LAY == LAY_EVEN ? a : b;
+            st<S, CP>(F[a], R.f, o.v, R.so(pa) + o.s);
+            st<S, CP>(F[b], R.f, o.v, R.so(pb) + o.s);
             if constexpr (HAS_G) {
-                st<S, CP>(E[a], R.g, nb.own, R.so(b));
-                st<S, CP>(E[b], R.g, nb.own, R.so(a));
+                st<S, CP>(E[a], R.g, o.v, R.so(pa) + o.s);
+                st<S, CP>(E[b], R.g, o.v, R.so(pb) + o.s);
             }
         }
     });

@@ -8,34 +8,54 @@
 namespace esbgk {
 
 // ---------------------------------------------------------------- step
-// One work-group sweeps cpi consecutive chunks of blockDim.x cells, so the
-// cache lines that straddle two chunks (the odd layout reads and writes
-// x +- c) are reused from its own CU's caches.
-template <class L, int S, bool ODD, bool HAS_G, int CP>
-__global__ __launch_bounds__(512) void k_step(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
-                                              uint32_t remap, uint32_t cpi) {
+// One fused collide-and-stream step of the cells of one domain.  The state is
+// read in layout LAY from (fb, gb) and written to (wfb, wgb): the same
+// storage for the A-A layouts, the other copy for LAY_PULL.
+// One work-group sweeps cpi consecutive chunks of blockDim.x cells.
+// ROW: every wave lies inside one x-row (nx % 64 == 0); see RowNbr.
+template <class L, int S, int LAY, bool HAS_G, int CP, bool ROW>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW ? (L::Q <= 37 ? 4 : 3) : 1))) void k_step(
+    char *fb, char *gb, char *wfb, char *wgb, uint32_t pb, uint32_t sb, Geom g, Coll cp, uint32_t remap,
+    uint32_t cpi) {
     const uint32_t blk = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const Sets R(fb, gb, pb, sb);
+    const Sets W = LAY == LAY_PULL ? Sets(wfb, wgb, pb, sb) : R;
     const uint32_t first = blk * blockDim.x * cpi + threadIdx.x;
     for (uint32_t k = 0; k < cpi; k++) {
         const uint32_t cell = first + k * blockDim.x;
         if (cell >= g.ncell) return;
-        Nbr<L, S> nb;
-        if constexpr (ODD) nb.init(cell, g);
-        else nb.own = cell * StoreBytes<S>::value;
         float F[L::Q], E[HAS_G ? L::Q : 1];
-        gather<L, S, ODD, HAS_G, CP>(R, nb, F, E);
-        collide<L, HAS_G>(cp, F, E);
-        scatter<L, S, ODD, HAS_G, CP>(R, nb, F, E);
+        if constexpr (ROW) {
+            RowNbr<L, S> nb;
+            nb.init(cell, g);
+            if (nb.inner) gather<L, S, LAY, HAS_G, CP>(R, nb.v, F, E);
+            else gather<L, S, LAY, HAS_G, CP>(R, nb.edge(), F, E);
+            collide<L, HAS_G>(cp, F, E);
+            if constexpr (LAY == LAY_PULL) {
+                scatter<L, S, LAY, HAS_G, CP>(W, nb.v, F, E);   // own cell only
+            } else {
+                if (nb.inner) scatter<L, S, LAY, HAS_G, CP>(W, nb.v, F, E);
+                else scatter<L, S, LAY, HAS_G, CP>(W, nb.edge(), F, E);
+            }
+        } else {
+            Nbr<L, S> nb;
+            if constexpr (LAY != LAY_EVEN) nb.init(cell, g);
+            else nb.own = cell * StoreBytes<S>::value;
+            gather<L, S, LAY, HAS_G, CP>(R, nb, F, E);
+            collide<L, HAS_G>(cp, F, E);
+            scatter<L, S, LAY, HAS_G, CP>(W, nb, F, E);
+        }
     }
 }
 
 // ---------------------------------------------------------------- init
-// fields: [rho - 1 | u_x | u_y (| u_z) | T - 1], ncell floats each.
-template <class L, int S, bool HAS_G>
-__global__ __launch_bounds__(256) void k_init(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, Coll cp,
+// fields: [rho - 1 | u_x | u_y (| u_z) | T - 1], ncell floats each.  Writes
+// the equilibrium of each cell in layout LAY (LAY_EVEN or LAY_PULL).
+template <class L, int S, int LAY, bool HAS_G>
+__global__ __launch_bounds__(256) void k_init(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
                                               const float *fields) {
     const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t ncell = g.ncell;
     if (cell >= ncell) return;
     constexpr int D = L::D;
     float u[3] = {0, 0, 0};
@@ -44,18 +64,29 @@ __global__ __launch_bounds__(256) void k_init(char *fb, char *gb, uint32_t pb, u
     float F[L::Q], E[HAS_G ? L::Q : 1];
     equilibrium<L, HAS_G>(cp, fields[cell], u, fields[(1 + D) * (uint64_t)ncell + cell], F, E);
     const Sets R(fb, gb, pb, sb);
-    const uint32_t own = cell * StoreBytes<S>::value;
-    // natural layout (step 0)
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-        st<S>(F[i], R.f, own, R.so(i));
-        if constexpr (HAS_G) st<S>(E[i], R.g, own, R.so(i));
-    }
+    Nbr<L, S> nb;
+    nb.init(cell, g);
+    st<S>(F[0], R.f, nb.own, 0);
+    if constexpr (HAS_G) st<S>(E[0], R.g, nb.own, 0);
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int a = 2 * p + 1, b = 2 * p + 2;
+        // direction a of this cell lives at (x - c_a, plane a) in the pull layout
+        const uint32_t la = LAY == LAY_PULL ? nb.template at<-cx, -cy, -cz>().v : nb.own;
+        const uint32_t lb = LAY == LAY_PULL ? nb.template at<cx, cy, cz>().v : nb.own;
+        st<S>(F[a], R.f, la, R.so(a));
+        st<S>(F[b], R.f, lb, R.so(b));
+        if constexpr (HAS_G) {
+            st<S>(E[a], R.g, la, R.so(a));
+            st<S>(E[b], R.g, lb, R.so(b));
+        }
+    });
 }
 
 // ---------------------------------------------------------------- moments
 // out: [rho - 1 | u (D) | T_eq - 1 | P - delta (D(D+1)/2, if with_P)]
-template <class L, int S, bool ODD, bool HAS_G>
+template <class L, int S, int LAY, bool HAS_G>
 __global__ __launch_bounds__(256) void k_moments(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
                                                  float *out, int with_P) {
     const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -65,7 +96,7 @@ __global__ __launch_bounds__(256) void k_moments(char *fb, char *gb, uint32_t pb
     nb.init(cell, g);
     const Sets R(fb, gb, pb, sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
-    gather<L, S, ODD, HAS_G>(R, nb, F, E);
+    gather<L, S, LAY, HAS_G>(R, nb, F, E);
     const CellState<D> cs = cell_moments<L, HAS_G>(cp, F, E);
     const uint64_t n = g.ncell;
     const float r = __builtin_sqrtf(cp.r2);
@@ -90,7 +121,7 @@ __global__ __launch_bounds__(256) void k_moments(char *fb, char *gb, uint32_t pb
 // out[k*Q + i] = f_i - w_i of listed cell k (unscaled, FP32); g after the f
 // block at offset n*Q.  list == nullptr: all cells, output as planes
 // out[i*ncell + k].
-template <class L, int S, bool ODD, bool HAS_G>
+template <class L, int S, int LAY, bool HAS_G>
 __global__ __launch_bounds__(256) void k_cells(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
                                                const uint32_t *list, uint32_t n, float *out) {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -101,7 +132,7 @@ __global__ __launch_bounds__(256) void k_cells(char *fb, char *gb, uint32_t pb, 
     nb.init(cell, g);
     const Sets R(fb, gb, pb, sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
-    gather<L, S, ODD, HAS_G>(R, nb, F, E);
+    gather<L, S, LAY, HAS_G>(R, nb, F, E);
     int sh[L::Q];
     sh[0] = 0;
 #pragma unroll
@@ -120,8 +151,9 @@ __global__ __launch_bounds__(256) void k_cells(char *fb, char *gb, uint32_t pb, 
 }
 
 // ---------------------------------------------------------------- write populations
-// in: scaled deviations as planes in natural order ([f planes | g planes]).
-template <class L, int S, bool ODD, bool HAS_G>
+// in: scaled deviations as planes in natural order ([f planes | g planes]),
+// stored in layout LAY.
+template <class L, int S, int LAY, bool HAS_G>
 __global__ __launch_bounds__(256) void k_write(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g,
                                                const float *in) {
     const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -136,14 +168,16 @@ __global__ __launch_bounds__(256) void k_write(char *fb, char *gb, uint32_t pb, 
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
         constexpr int a = 2 * p + 1, b = 2 * p + 2;
-        // value of direction a at this cell lives at (x - c, plane b) in the odd layout
-        const uint32_t la = ODD ? nb.template at<-cx, -cy, -cz>() : nb.own;
-        const uint32_t lb = ODD ? nb.template at<cx, cy, cz>() : nb.own;
-        st<S>(in[a * n + cell], R.f, la, R.so(ODD ? b : a));
-        st<S>(in[b * n + cell], R.f, lb, R.so(ODD ? a : b));
+        // direction a of this cell lives at (x - c_a) in the odd and pull layouts
+        constexpr bool SHIFT = LAY != LAY_EVEN;
+        constexpr int pa = LAY == LAY_ODD ? b : a, pb_ = LAY == LAY_ODD ? a : b;
+        const uint32_t la = SHIFT ? nb.template at<-cx, -cy, -cz>().v : nb.own;
+        const uint32_t lb = SHIFT ? nb.template at<cx, cy, cz>().v : nb.own;
+        st<S>(in[a * n + cell], R.f, la, R.so(pa));
+        st<S>(in[b * n + cell], R.f, lb, R.so(pb_));
         if constexpr (HAS_G) {
-            st<S>(in[(L::Q + a) * n + cell], R.g, la, R.so(ODD ? b : a));
-            st<S>(in[(L::Q + b) * n + cell], R.g, lb, R.so(ODD ? a : b));
+            st<S>(in[(L::Q + a) * n + cell], R.g, la, R.so(pa));
+            st<S>(in[(L::Q + b) * n + cell], R.g, lb, R.so(pb_));
         }
     });
 }
@@ -177,64 +211,77 @@ inline uint32_t nblocks(uint64_t n, int block) { return (uint32_t)((n + block - 
 
 template <class L, int S>
 struct OpsImpl {
+    // Calls K<LAY>() with the layout as a template argument.
+    template <class K>
+    static void by_layout(int lay, K &&k) {
+        if (lay == LAY_ODD) k(std::integral_constant<int, LAY_ODD>{});
+        else if (lay == LAY_PULL) k(std::integral_constant<int, LAY_PULL>{});
+        else k(std::integral_constant<int, LAY_EVEN>{});
+    }
     template <int CP>
-    static void step_cp(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd,
-                        bool has_g, int block, int remap, int cpi, hipStream_t s) {
+    static void step_cp(char *fb, char *gb, char *wfb, char *wgb, uint32_t pb, uint32_t sb, const Geom &g,
+                        const Coll &c, int lay, bool has_g, int block, int remap, int cpi, hipStream_t s) {
         const uint32_t nb = nblocks(g.ncell, block * cpi);
         const uint32_t k = (uint32_t)cpi;
-        if (odd) {
-            if (has_g) k_step<L, S, true, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
-            else k_step<L, S, true, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
-        } else {
-            if (has_g) k_step<L, S, false, true, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
-            else k_step<L, S, false, false, CP><<<nb, block, 0, s>>>(fb, gb, pb, sb, g, c, remap, k);
-        }
+        // waves start at multiples of 64 cells (block is a multiple of 64)
+        const bool row = g.nx % 64 == 0 && lay != LAY_EVEN;
+        by_layout(lay, [&](auto ly) {
+            constexpr int LY = decltype(ly)::value;
+            if (row) {
+                if constexpr (LY != LAY_EVEN) {
+                    if (has_g) k_step<L, S, LY, true, CP, true><<<nb, block, 0, s>>>(fb, gb, wfb, wgb, pb, sb, g, c, remap, k);
+                    else k_step<L, S, LY, false, CP, true><<<nb, block, 0, s>>>(fb, gb, wfb, wgb, pb, sb, g, c, remap, k);
+                }
+            } else {
+                if (has_g) k_step<L, S, LY, true, CP, false><<<nb, block, 0, s>>>(fb, gb, wfb, wgb, pb, sb, g, c, remap, k);
+                else k_step<L, S, LY, false, CP, false><<<nb, block, 0, s>>>(fb, gb, wfb, wgb, pb, sb, g, c, remap, k);
+            }
+        });
     }
     // policy 0: default caching; 1: non-temporal loads and stores
-    static void step(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd,
-                     bool has_g, const Tile &t, hipStream_t s) {
-        if (t.policy) step_cp<2>(fb, gb, pb, sb, g, c, odd, has_g, t.block, t.remap, t.cpi, s);
-        else step_cp<0>(fb, gb, pb, sb, g, c, odd, has_g, t.block, t.remap, t.cpi, s);
+    static void step(char *fb, char *gb, char *wfb, char *wgb, uint32_t pb, uint32_t sb, const Geom &g,
+                     const Coll &c, int lay, bool has_g, const Tile &t, hipStream_t s) {
+        if (t.policy) step_cp<2>(fb, gb, wfb, wgb, pb, sb, g, c, lay, has_g, t.block, t.remap, t.cpi, s);
+        else step_cp<0>(fb, gb, wfb, wgb, pb, sb, g, c, lay, has_g, t.block, t.remap, t.cpi, s);
     }
-    static void init(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
-                     hipStream_t s) {
-        const uint32_t nb = nblocks(ncell, 256);
-        if (has_g) k_init<L, S, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, ncell, c, fields);
-        else k_init<L, S, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, ncell, c, fields);
+    static void init(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, const float *fields,
+                     int lay, bool has_g, hipStream_t s) {
+        const uint32_t nb = nblocks(g.ncell, 256);
+        if (lay == LAY_PULL) {
+            if (has_g) k_init<L, S, LAY_PULL, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, fields);
+            else k_init<L, S, LAY_PULL, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, fields);
+        } else {
+            if (has_g) k_init<L, S, LAY_EVEN, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, fields);
+            else k_init<L, S, LAY_EVEN, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, fields);
+        }
     }
-    static void moments(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
+    static void moments(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, int lay, bool has_g,
                         float *out, bool with_P, hipStream_t s) {
         const uint32_t nb = nblocks(g.ncell, 256);
         const int wp = with_P ? 1 : 0;
-        if (odd) {
-            if (has_g) k_moments<L, S, true, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
-            else k_moments<L, S, true, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
-        } else {
-            if (has_g) k_moments<L, S, false, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
-            else k_moments<L, S, false, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
-        }
+        by_layout(lay, [&](auto ly) {
+            constexpr int LY = decltype(ly)::value;
+            if (has_g) k_moments<L, S, LY, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
+            else k_moments<L, S, LY, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, out, wp);
+        });
     }
-    static void cells(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
+    static void cells(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, int lay, bool has_g,
                       const uint32_t *list, uint32_t n, float *out, hipStream_t s) {
         const uint32_t nb = nblocks(n, 256);
-        if (odd) {
-            if (has_g) k_cells<L, S, true, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
-            else k_cells<L, S, true, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
-        } else {
-            if (has_g) k_cells<L, S, false, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
-            else k_cells<L, S, false, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
-        }
+        by_layout(lay, [&](auto ly) {
+            constexpr int LY = decltype(ly)::value;
+            if (has_g) k_cells<L, S, LY, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
+            else k_cells<L, S, LY, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, list, n, out);
+        });
     }
-    static void write(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, bool odd, bool has_g, const float *in,
+    static void write(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, int lay, bool has_g, const float *in,
                       hipStream_t s) {
         const uint32_t nb = nblocks(g.ncell, 256);
-        if (odd) {
-            if (has_g) k_write<L, S, true, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
-            else k_write<L, S, true, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
-        } else {
-            if (has_g) k_write<L, S, false, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
-            else k_write<L, S, false, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
-        }
+        by_layout(lay, [&](auto ly) {
+            constexpr int LY = decltype(ly)::value;
+            if (has_g) k_write<L, S, LY, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
+            else k_write<L, S, LY, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, in);
+        });
     }
     static void plane_sums(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, int q, bool has_g, double *partials,
                            uint32_t nchunks, hipStream_t s) {

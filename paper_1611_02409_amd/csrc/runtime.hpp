@@ -37,8 +37,13 @@ struct DomainSetup {
     Coll coll;
     Geom geom;
     int npop;
+    int codec;       // ESBGK_F32, ESBGK_F16_DEV or ESBGK_BF16_DEV
+    int copies;      // 1: A-A in place; 2: two-copy pull
     uint32_t esize;
-    uint64_t plane_bytes, bytes;
+    uint64_t plane_bytes;
+    uint64_t set_stride;   // bytes from the f set to the g set
+    uint64_t copy_bytes;   // bytes of one copy of the state
+    uint64_t bytes;        // all population storage
 };
 
 int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, const int64_t *dims, int storage,
@@ -59,17 +64,19 @@ struct Tile {
     int cpi = 1;       // chunks of `block` cells per work-group
 };
 
-// Kernel dispatch of one (lattice, storage) combination.
+// Kernel dispatch of one (lattice, storage) combination.  lay is the layout
+// of the stored state (LAY_EVEN, LAY_ODD or LAY_PULL); a step reads (fb, gb)
+// and writes (wfb, wgb), which are the same storage except for LAY_PULL.
 struct Ops {
-    void (*step)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
-                 const Tile &t, hipStream_t s);
-    void (*init)(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, const Coll &c, const float *fields, bool has_g,
-                 hipStream_t s);
-    void (*moments)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g, float *out,
-                    bool with_P, hipStream_t s);
-    void (*cells)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, bool odd, bool has_g,
+    void (*step)(char *fb, char *gb, char *wfb, char *wgb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c,
+                 int lay, bool has_g, const Tile &t, hipStream_t s);
+    void (*init)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, const float *fields,
+                 int lay, bool has_g, hipStream_t s);
+    void (*moments)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, int lay, bool has_g,
+                    float *out, bool with_P, hipStream_t s);
+    void (*cells)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, int lay, bool has_g,
                   const uint32_t *list, uint32_t n, float *out, hipStream_t s);
-    void (*write)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, bool odd, bool has_g, const float *in,
+    void (*write)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, int lay, bool has_g, const float *in,
                   hipStream_t s);
     void (*plane_sums)(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, int nplanes_per_set, bool has_g,
                        double *partials, uint32_t nchunks, hipStream_t s);
@@ -78,7 +85,7 @@ struct Ops {
 const Ops *get_ops(int D, int Q, int storage);
 
 // Final FP64 reduction of plane sums into totals (one block on the GPU).
-void launch_totals_final(const double *partials, uint32_t nchunks, const LatticeConsts &lc, int npop, bool odd,
+void launch_totals_final(const double *partials, uint32_t nchunks, const LatticeConsts &lc, int npop, bool opp_planes,
                          uint64_t ncell, double hN, double *out, hipStream_t s);
 
 }  // namespace esbgk

@@ -81,6 +81,7 @@ def test_create_rejects_bad_shapes_without_a_device(esb):
     lib = esb._lib
     h = ctypes.c_void_p()
     for D, Q, dims, storage, code in [(2, 35, (8, 8), 0, -2), (2, 37, (2, 8), 0, -1), (2, 37, (8, 8), 7, -1),
+                                      (2, 37, (8, 8), 0x13, -1), (2, 37, (8, 8), 0x20, -1),
                                       (2, 37, (70000, 70000), 0, -2), (3, 39, (8, 8, 2), 0, -1)]:
         d = (ctypes.c_int64 * 3)(*(list(dims) + [1] * (3 - len(dims))))
         rc = lib.esbgk_create(D, Q, 3, 0.71, 0.8, d, storage, ctypes.byref(h))
@@ -93,6 +94,21 @@ def test_storage_bytes(esb):
     assert n == 2 * 37 * 4096 * 4096 * 4
     assert esb.storage_bytes(2, 37, 0, (4096, 4096), "f16") == 37 * 4096 * 4096 * 2
     assert esb.storage_bytes(3, 39, 2, (256, 256, 256), "bf16") == 2 * 39 * 256 ** 3 * 2
+    # two-copy pull keeps two whole copies (each set 256-byte aligned)
+    assert esb.storage_bytes(2, 37, 3, (4096, 4096), "f32", "pull") == 2 * n
+    assert esb.storage_bytes(2, 37, 1, (33, 35), "f16", "pull") == 2 * 2 * ((37 * 33 * 35 * 2 + 255) // 256 * 256)
+    with pytest.raises(ValueError):
+        esb.storage_bytes(2, 37, 3, (64, 64), "f32", "push")
+
+
+def test_batch_rejects_pull_streaming_without_a_device(esb):
+    lib = esb._lib
+    desc = (esb.DomainDesc * 1)()
+    desc[0].N_f, desc[0].Pr, desc[0].tau, desc[0].kappa = 3, 0.71, 0.6, 0.2
+    desc[0].dims[0], desc[0].dims[1], desc[0].dims[2] = 64, 64, 1
+    h = ctypes.c_void_p()
+    assert lib.esbgk_batch_create(2, 37, 1, desc, esb.PULL, ctypes.byref(h)) == -2
+    assert "ESBGK_PULL" in lib.esbgk_last_error().decode()
 
 
 def test_null_handles_are_rejected(esb):

@@ -27,6 +27,7 @@ DOMS = [
     dict(dims=(96, 64), Nf=3, Pr=1.3, tau=0.55),
     dict(dims=(20, 70), Nf=0, Pr=0.8, tau=0.75, kappa=0.4),
     dict(dims=(130, 12), Nf=1, Pr=1.9, tau=0.95),
+    dict(dims=(192, 10), Nf=3, Pr=0.71, tau=0.6),
 ]
 
 

@@ -34,8 +34,8 @@ def perm_to_oracle(D, Q):
     return np.array([oc.index(tuple(c)) for c in li["c"]]), li
 
 
-def gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, storage="f32", kappa=0.2):
-    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, kappa=kappa)
+def gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, storage="f32", kappa=0.2, streaming="aa"):
+    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, kappa=kappa, streaming=streaming)
     lat.init_fields(*fields)
     if steps:
         lat.step(steps)
@@ -49,6 +49,10 @@ CASES = [
     (2, 37, 1, 0.5, 1.2, (33, 35)),
     (3, 39, 2, 0.71, 0.7, (12, 10, 8)),
     (2, 33, 3, 0.71, 2 / 3, (40, 24)),
+    # rows of whole waves (nx % 64 == 0) with waves away from both row ends
+    (2, 37, 3, 0.71, 0.6, (192, 20)),
+    (3, 39, 2, 0.71, 0.7, (192, 4, 5)),
+    (2, 33, 1, 1.3, 0.8, (256, 8)),
 ]
 
 
@@ -122,13 +126,14 @@ def test_totals_match_oracle_and_are_conserved(D, Q, Nf, Pr, tau, dims):
     assert abs(t1[0] - t0[0]) / n < 1e-7
 
 
+@pytest.mark.parametrize("dims", [(40, 32), (192, 16)])
 @pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 1.6e-2)])
-def test_reduced_storage_one_step(storage, tol):
+def test_reduced_storage_one_step(storage, tol, dims):
     """FP16 / BF16 storage of scaled deviations: after init and after one
     step the stored values differ from the oracle by the storage rounding of
     a deviation of this size (relative 2^-11 for FP16, 2^-8 for BF16, of
     values up to ~0.5 w_i, plus the FP32 collision)."""
-    D, Q, Nf, Pr, tau, dims = 2, 37, 3, 0.71, 0.6, (40, 32)
+    D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
     fields = workloads.random_state(dims, seed=15)
     perm, li = perm_to_oracle(D, Q)
     for steps in (0, 1, 2):
@@ -184,14 +189,15 @@ def test_full_size_one_step_sampled(steps0):
     assert ef < 1e-6 and eg < 1e-6
 
 
-def test_save_load_continues_bitwise(tmp_path):
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+def test_save_load_continues_bitwise(tmp_path, streaming):
     dims = (32, 32)
     fields = workloads.random_state(dims, seed=16)
-    a = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 10)
-    b = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 5)
+    a = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 10, streaming=streaming)
+    b = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 5, streaming=streaming)
     p = str(tmp_path / "ck.bin")
     b.save(p)
-    c = esb.Lattice(2, 37, 3, 0.71, 0.6, dims)
+    c = esb.Lattice(2, 37, 3, 0.71, 0.6, dims, streaming=streaming)
     c.load(p)
     assert c.steps == 5
     c.step(5)
@@ -200,13 +206,14 @@ def test_save_load_continues_bitwise(tmp_path):
     assert np.array_equal(fa, fc) and np.array_equal(ga, gc)
 
 
-def test_write_populations_roundtrip():
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+def test_write_populations_roundtrip(streaming):
     D, Q, Nf, dims = 2, 37, 3, (24, 20)
     fields = workloads.random_state(dims, seed=17)
     sim = oracle_run(D, Q, Nf, 0.71, 0.6, dims, fields, 3)
     perm, li = perm_to_oracle(D, Q)
     fo, go = sim.get_pops()
-    lat = gpu_run(D, Q, Nf, 0.71, 0.6, dims, fields, 3)      # odd layout
+    lat = gpu_run(D, Q, Nf, 0.71, 0.6, dims, fields, 3, streaming=streaming)   # A-A: odd layout
     lat.write_populations(fo[perm], go[perm])
     fg, gg = lat.read_populations()
     assert pop_error(li["w"], fg, fo[perm]) < 1e-7
@@ -223,11 +230,12 @@ def test_write_populations_roundtrip():
     [(0, 256, 1, 2, 4), (1, 128, 2, 1, 3)],
     [(0, 512, 2, 1, 64), (1, 256, 1, 2, 1)],
 ])
-def test_launch_shape_does_not_change_results(tiles):
+@pytest.mark.parametrize("dims", [(77, 53), (256, 7)])
+def test_launch_shape_does_not_change_results(tiles, dims):
     """Work-group size, order, cache policy and chunks per work-group, set
     per parity, leave every population bitwise unchanged (ragged grid, so
-    partial chunks and partial work-groups are exercised)."""
-    dims = (77, 53)
+    partial chunks and partial work-groups are exercised; and rows of whole
+    waves)."""
     fields = workloads.random_state(dims, seed=21)
     ref = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 5)
     lat = esb.Lattice(2, 37, 3, 0.71, 0.6, dims)
@@ -239,10 +247,11 @@ def test_launch_shape_does_not_change_results(tiles):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
-def test_autotune_restores_state(tmp_path):
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+def test_autotune_restores_state(tmp_path, streaming):
     dims = (96, 80)
     fields = workloads.random_state(dims, seed=22)
-    lat = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 3)
+    lat = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 3, streaming=streaming)
     before = lat.read_populations()
     cache = str(tmp_path / "tune.txt")
     even, odd = lat.autotune(cache_path=cache)
@@ -250,5 +259,42 @@ def test_autotune_restores_state(tmp_path):
     after = lat.read_populations()
     assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
     # a second handle picks the cached shapes without timing
-    lat2 = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 0)
+    lat2 = gpu_run(2, 37, 3, 0.71, 0.6, dims, fields, 0, streaming=streaming)
     assert lat2.autotune(cache_path=cache) == (even, odd)
+
+
+PULL_CASES = [
+    (2, 37, 3, 0.71, 0.6, (64, 48), "f32"),
+    (2, 37, 1, 0.5, 1.2, (33, 35), "f32"),
+    (2, 37, 3, 0.71, 0.6, (192, 20), "f16"),
+    (2, 37, 0, 2.0, 0.9, (40, 36), "bf16"),
+    (3, 39, 2, 0.71, 0.7, (12, 10, 8), "f32"),
+    (3, 39, 2, 0.71, 0.7, (192, 4, 5), "f32"),
+    (2, 33, 1, 1.3, 0.8, (256, 8), "f16"),
+]
+
+
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,dims,storage", PULL_CASES)
+def test_pull_streaming_equals_aa_bitwise(D, Q, Nf, Pr, tau, dims, storage):
+    """Two-copy pull streaming performs the same arithmetic on the same
+    values as A-A, so every population and moment agrees bit for bit after
+    any number of steps; totals agree to FP64 summation order."""
+    fields = workloads.random_state(dims, seed=31)
+    a = gpu_run(D, Q, Nf, Pr, tau, dims, fields, 0, storage=storage)
+    p = gpu_run(D, Q, Nf, Pr, tau, dims, fields, 0, storage=storage, streaming="pull")
+    done = 0
+    for target in (1, 2, 3, 8):
+        a.step(target - done)
+        p.step(target - done)
+        done = target
+        fa, ga = a.read_populations()
+        fp, gp = p.read_populations()
+        assert np.array_equal(fa, fp) and np.array_equal(ga, gp), (storage, target)
+        ma, mp = a.read_moments(with_P=True), p.read_moments(with_P=True)
+        for k in ("rho", "u", "T", "P"):
+            assert np.array_equal(ma[k], mp[k]), (k, target)
+        ta, tp = a.totals(), p.totals()
+        assert np.allclose(ta, tp, rtol=0, atol=1e-12 * float(np.prod(dims))), (ta, tp)
+        sample = np.array([0, 5, int(np.prod(dims)) - 1])
+        ca, cp = a.read_cells(sample), p.read_cells(sample)
+        assert np.array_equal(ca[0], cp[0]) and np.array_equal(ca[1], cp[1])
