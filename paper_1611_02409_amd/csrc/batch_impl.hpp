@@ -77,7 +77,7 @@ __device__ __forceinline__ void tile_step(char *base, const DomDev &dd, uint32_t
     const Sets R(base + dd.f_off, HAS_G ? base + dd.g_off : nullptr, dd.pb, dd.sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
     gather<L, S, ODD, HAS_G, CP>(R, nb, F, E);
-    collide<L, HAS_G>(dd.coll, F, E);
+    collide<L, HAS_G, TargetReal<S>>(dd.coll, F, E);
     scatter<L, S, ODD, HAS_G, CP>(R, nb, F, E);
 }
 
@@ -169,10 +169,11 @@ __device__ __forceinline__ void persistent_body(char *base, const BatchDev &b) {
 }
 
 // Register budget: three waves per SIMD where the code fits in 168 VGPRs
-// without spilling (FP32, BF16); FP16 storage keeps the compiler's choice.
+// without spilling (BF16); FP32 storage (FP64 target) and FP16 storage keep
+// the compiler's choice.
 template <class L, int S, int CP>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_persistent(char *base,
-                                                                                                  BatchDev b) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(S == ST_BF16 && L::Q <= 37 ? 3 : 1))) void k_batch_persistent(
+    char *base, BatchDev b) {
     persistent_body<L, S, CP>(base, b);
 }
 

@@ -57,17 +57,23 @@ Coll make_coll(const LatticeConsts &lc, const double prm[4], int D, int Nf, doub
     c.omega = (float)prm[0];
     c.kappa = (float)kappa;
     c.nu = (float)prm[2];
-    c.r2 = (float)(lc.r * lc.r);
+    const double r2 = lc.r * lc.r;
+    c.r2 = (float)r2;
+    c.r2_lo = (float)(r2 - (double)c.r2);
     c.hN = (float)(0.5 * Nf);
-    c.two_over_nf = Nf > 0 ? (float)(2.0 / Nf) : 0.f;
+    const double tnf = Nf > 0 ? 2.0 / Nf : 0.0;
+    c.two_over_nf = (float)tnf;
+    c.two_over_nf_lo = (float)(tnf - (double)c.two_over_nf);
     c.cD = (float)(double(D) / double(D + Nf));
     c.cN = (float)(double(Nf) / double(D + Nf));
     for (int s = 0; s < MAX_SHELL; s++) {
         if (s < lc.nshell) {
-            c.wh[s] = (float)std::ldexp(lc.wshell[s], lc.scale_exp[s]);
+            const double w = std::ldexp(lc.wshell[s], lc.scale_exp[s]);
+            c.wh[s] = (float)w;
+            c.wl[s] = (float)(w - (double)c.wh[s]);
             c.isc[s] = (float)std::ldexp(1.0, -lc.scale_exp[s]);
         } else {
-            c.wh[s] = 0.f;
+            c.wh[s] = c.wl[s] = 0.f;
             c.isc[s] = 0.f;
         }
     }

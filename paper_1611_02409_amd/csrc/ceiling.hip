@@ -1,5 +1,6 @@
-// Measured bandwidth ceiling of the step kernels' access pattern: an in-place
-// read-modify-write stream over 74 planes, with no collision arithmetic.
+// Measured bandwidth ceiling of the step kernels' access pattern: 74-plane
+// read and write streams (in place or between two buffers), no arithmetic.
+#include <algorithm>
 #include <vector>
 
 #include "runtime.hpp"
@@ -7,11 +8,14 @@
 namespace esbgk {
 namespace {
 
+// Reads 74 planes of each cell from src and writes them to dst (dst == src:
+// in place, as A-A does; another buffer: as two-copy pull does).
 template <int NP>
-__global__ __launch_bounds__(256) void k_stream_rw(char *p, uint32_t ncell, uint32_t set_bytes) {
+__global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_t ncell, uint32_t set_bytes) {
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    const Sets R(p, p + set_bytes, ncell * 4u, set_bytes);
+    const Sets R(src, src + set_bytes, ncell * 4u, set_bytes);
+    const Sets W(dst, dst + set_bytes, ncell * 4u, set_bytes);
     float v[NP];
 #pragma unroll
     for (int i = 0; i < NP; i++) v[i] = ld<ST_F32>(i < NP / 2 ? R.f : R.g, c * 4u, R.so(i % (NP / 2)));
@@ -19,7 +23,7 @@ __global__ __launch_bounds__(256) void k_stream_rw(char *p, uint32_t ncell, uint
 #pragma unroll
     for (int i = 0; i < NP; i++) s += v[i];
 #pragma unroll
-    for (int i = 0; i < NP; i++) st<ST_F32>(v[i] + s * 1e-30f, i < NP / 2 ? R.f : R.g, c * 4u, R.so(i % (NP / 2)));
+    for (int i = 0; i < NP; i++) st<ST_F32>(v[i] + s * 1e-30f, i < NP / 2 ? W.f : W.g, c * 4u, W.so(i % (NP / 2)));
 }
 
 }  // namespace
@@ -27,6 +31,9 @@ __global__ __launch_bounds__(256) void k_stream_rw(char *p, uint32_t ncell, uint
 
 using namespace esbgk;
 
+// Best of three placements of the pattern: in place on each of two buffers
+// allocated one after the other, and a copy from one to the other.  (Where a
+// buffer lands in HBM moves such streams by a few per cent.)
 extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     clear_error();
     if (cells < 256 || cells > (int64_t)14000000 * 2 || reps < 1 || !gbps) {
@@ -35,31 +42,40 @@ extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     }
     const uint32_t n = (uint32_t)cells;
     const uint32_t set_bytes = 37u * n * 4u;
-    char *p = nullptr;
-    ESBGK_HIP(hipMalloc(&p, 2ull * set_bytes));
-    hipEvent_t e0, e1;
+    char *p[2] = {nullptr, nullptr};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ESBGK_OK;
-    if (hipMemset(p, 0, 2ull * set_bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-        hipEventCreate(&e1) != hipSuccess) {
-        set_error("setup failed");
-        (void)hipFree(p);
-        return ESBGK_EDEVICE;
+    for (int k = 0; k < 2 && rc == ESBGK_OK; k++) {
+        if (hipMalloc(&p[k], 2ull * set_bytes) != hipSuccess || hipMemset(p[k], 0, 2ull * set_bytes) != hipSuccess) {
+            set_error("allocation of the stream buffers failed");
+            rc = ESBGK_ENOMEM;
+        }
+    }
+    if (rc == ESBGK_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+        set_error("event creation failed");
+        rc = ESBGK_EDEVICE;
     }
     const uint32_t nb = (n + 255) / 256;
-    for (int w = 0; w < 2; w++) k_stream_rw<74><<<nb, 256>>>(p, n, set_bytes);
-    (void)hipEventRecord(e0, nullptr);
-    for (int r = 0; r < reps; r++) k_stream_rw<74><<<nb, 256>>>(p, n, set_bytes);
-    (void)hipEventRecord(e1, nullptr);
-    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-        set_error("stream kernel failed");
-        rc = ESBGK_EDEVICE;
-    } else {
+    double best = 0;
+    for (int pass = 0; pass < 3 && rc == ESBGK_OK; pass++) {
+        char *src = p[pass == 1 ? 1 : 0], *dst = p[pass == 0 ? 0 : 1];
+        for (int w = 0; w < 2; w++) k_stream_rw<74><<<nb, 256>>>(src, dst, n, set_bytes);
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; r++) k_stream_rw<74><<<nb, 256>>>(src, dst, n, set_bytes);
+        (void)hipEventRecord(e1, nullptr);
+        if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            set_error("stream kernel failed");
+            rc = ESBGK_EDEVICE;
+            break;
+        }
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        *gbps = 2.0 * 2.0 * set_bytes * reps / (ms * 1e-3) / 1e9;
+        best = std::max(best, 2.0 * 2.0 * set_bytes * reps / (ms * 1e-3) / 1e9);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(p);
+    if (rc == ESBGK_OK) *gbps = best;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    for (char *q : p)
+        if (q) (void)hipFree(q);
     return rc;
 }

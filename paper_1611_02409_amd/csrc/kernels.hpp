@@ -70,24 +70,40 @@ struct Geom {
     FastDiv by_nx, by_nxy;
 };
 
-// Collision constants of one domain (FP32).
+// Collision constants of one domain (FP32).  The constants that multiply
+// first-order deviations in the moments and the target (r^2, 2/N_f and the
+// weights) also carry their FP32 rounding error as a second float (_lo):
+// rounded once, they would make the FP32 scheme a slightly different
+// lattice (sound speed off by a few 1e-8), an error that grows linearly
+// with the acoustic phase travelled.
 struct Coll {
     float omega;        // heat-flux (collision) rate
     float kappa, nu;    // Lambda / T_rel blend and ES parameter
-    float r2;           // r^2 (xi = r c)
+    float r2, r2_lo;    // r^2 (xi = r c)
     float hN;           // N_f / 2
-    float two_over_nf;  // 2 / N_f (0 when N_f = 0)
+    float two_over_nf, two_over_nf_lo;   // 2 / N_f (0 when N_f = 0)
     float cD, cN;       // D/(D+N_f), N_f/(D+N_f)
     float wh[MAX_SHELL];   // s w per shell
+    float wl[MAX_SHELL];   // s w - wh per shell
     float isc[MAX_SHELL];  // 1/s per shell
 };
 
-template <int C>
-__device__ __forceinline__ float acc_c(float acc, float v) {
+// x * (hi + lo) with the product of the two-float constant formed exactly
+// up to the final rounding
+__device__ __forceinline__ float mul2(float x, float hi, float lo) { return __builtin_fmaf(x, hi, x * lo); }
+template <class R>
+__device__ __forceinline__ R mul_r2(R x, float hi, float lo) {
+    if constexpr (sizeof(R) == 8) return x * (double(hi) + double(lo));
+    else return __builtin_fmaf(x, hi, x * lo);
+}
+
+template <int C, class T>
+__device__ __forceinline__ T acc_c(T acc, T v) {
     if constexpr (C == 0) return acc;
     else if constexpr (C == 1) return acc + v;
     else if constexpr (C == -1) return acc - v;
-    else return __builtin_fmaf(float(C), v, acc);
+    else if constexpr (sizeof(T) == 8) return __builtin_fma(T(C), v, acc);
+    else return __builtin_fmaf(T(C), v, acc);
 }
 
 template <int C>
@@ -405,16 +421,30 @@ struct CellState {
 
 // Invariants of the target: with Ah = r^2 A, uh = r^2 u/r (= r^2 J/rho in
 // lattice form), the per-direction quantities are dot products with the
-// integer velocity c.
-template <int D>
+// integer velocity c.  R is the precision the target is evaluated in: FP64
+// with FP32 storage (in FP32 the rounding of the target leaves a bias that a
+// weakly damped acoustic or entropy wave integrates over thousands of steps,
+// a few 1e-8 absolute in rho and u after 5000 steps; in FP64 that part is
+// 1e-10, for about 600 FP64 operations per cell on a kernel bound by HBM),
+// FP32 with FP16/BF16 storage, whose rounding dominates anyway.
+template <int D, class R>
 struct TargetInv {
-    float uh[3];     // s1 = uh . c
-    float Ah[6];     // a = c . Ah . c
-    float wv[3];     // b = wv . c
-    float A2[6];     // c4 = c . A2 . c
-    float tU;        // t + U
-    float K24;       // q/4 + m/2
+    R uh[3];     // s1 = uh . c
+    R Ah[6];     // a = c . Ah . c
+    R wv[3];     // b = wv . c
+    R A2[6];     // c4 = c . A2 . c
+    R tU;        // t + U
+    R K24;       // q/4 + m/2
 };
+
+template <int S>
+using TargetReal = std::conditional_t<S == ST_F32, double, float>;
+
+template <class R>
+__device__ __forceinline__ R fma_r(R a, R b, R c) {
+    if constexpr (sizeof(R) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
 
 __device__ __forceinline__ int sym_idx(int a, int b) {
     // (0,0)->0 (0,1)->1 (0,2)->2 (1,1)->3 (1,2)->4 (2,2)->5
@@ -422,12 +452,17 @@ __device__ __forceinline__ int sym_idx(int a, int b) {
 }
 
 // Target invariants from A (physical, symmetric, 6 slots) and the
-// lattice-unit velocity ut = J/rho.
-template <int D>
-__device__ __forceinline__ TargetInv<D> target_inv(const float *A, const float *ut, float r2) {
-    TargetInv<D> T;
-    float t = 0, U = 0, q = 0, m = 0;
-    float Au[3] = {0, 0, 0};
+// lattice-unit velocity ut = J/rho; r^2 = r2_hi + r2_lo.
+template <int D, class R>
+__device__ __forceinline__ TargetInv<D, R> target_inv(const float *Af, const float *utf, float r2_hi, float r2_lo) {
+    TargetInv<D, R> T;
+    R A[6], ut[3];
+#pragma unroll
+    for (int k = 0; k < 6; k++) A[k] = Af[k];
+#pragma unroll
+    for (int k = 0; k < 3; k++) ut[k] = utf[k];
+    R t = 0, U = 0, q = 0, m = 0;
+    R Au[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; a++) {
         t += A[sym_idx(a, a)];
@@ -438,31 +473,31 @@ __device__ __forceinline__ TargetInv<D> target_inv(const float *A, const float *
 #pragma unroll
     for (int a = 0; a < D; a++) {
         m += ut[a] * Au[a];
-        T.uh[a] = r2 * ut[a];
-        T.wv[a] = r2 * Au[a];
+        T.uh[a] = mul_r2(ut[a], r2_hi, r2_lo);   // first order in u
+        T.wv[a] = R(r2_hi) * Au[a];
     }
 #pragma unroll
     for (int a = 0; a < D; a++)
 #pragma unroll
         for (int b = a; b < D; b++) {
-            float s = 0;
+            R s = 0;
 #pragma unroll
             for (int k = 0; k < D; k++) s += A[sym_idx(a, k)] * A[sym_idx(k, b)];
-            T.A2[sym_idx(a, b)] = r2 * s;
-            T.Ah[sym_idx(a, b)] = r2 * A[sym_idx(a, b)];
-            q += (a == b ? 1.f : 2.f) * A[sym_idx(a, b)] * A[sym_idx(a, b)];
+            T.A2[sym_idx(a, b)] = R(r2_hi) * s;
+            T.Ah[sym_idx(a, b)] = mul_r2(A[sym_idx(a, b)], r2_hi, r2_lo);   // first order in A
+            q += (a == b ? R(1) : R(2)) * A[sym_idx(a, b)] * A[sym_idx(a, b)];
         }
-    U *= r2;
-    m *= r2;
+    U *= R(r2_hi);
+    m *= R(r2_hi);
     T.tU = t + U;
-    T.K24 = 0.25f * q + 0.5f * m;
+    T.K24 = R(0.25) * q + R(0.5) * m;
     return T;
 }
 
 // E - 1 and O for the velocity pair +-c (c compile-time).
-template <int D, int CX, int CY, int CZ>
-__device__ __forceinline__ void target_pair(const TargetInv<D> &T, float &Em1, float &O) {
-    float s1 = 0, a = 0, b = 0, c4 = 0;
+template <int D, int CX, int CY, int CZ, class R>
+__device__ __forceinline__ void target_pair(const TargetInv<D, R> &T, R &Em1, R &O) {
+    R s1 = 0, a = 0, b = 0, c4 = 0;
     s1 = acc_c<CX>(s1, T.uh[0]);
     s1 = acc_c<CY>(s1, T.uh[1]);
     b = acc_c<CX>(b, T.wv[0]);
@@ -483,23 +518,35 @@ __device__ __forceinline__ void target_pair(const TargetInv<D> &T, float &Em1, f
         c4 = acc_c<2 * CY * CZ>(c4, T.A2[4]);
         c4 = acc_c<CZ * CZ>(c4, T.A2[5]);
     }
-    const float al = a - T.tU;
-    const float s2 = s1 * s1;
-    const float h = al + s2;
-    float e = h * __builtin_fmaf(0.125f, h, 0.5f);
-    e = __builtin_fmaf(-s2 * (1.0f / 12.0f), s2, e);
-    e = __builtin_fmaf(-0.5f, c4, e);
-    e = __builtin_fmaf(-b, s1, e);
+    const R al = a - T.tU;
+    const R s2 = s1 * s1;
+    const R h = al + s2;
+    R e = h * fma_r(R(0.125), h, R(0.5));
+    e = fma_r(-s2 * R(1.0 / 12.0), s2, e);
+    e = fma_r(R(-0.5), c4, e);
+    e = fma_r(-b, s1, e);
     Em1 = e + T.K24;
-    const float k = __builtin_fmaf(s2, 1.0f / 6.0f, __builtin_fmaf(0.5f, al, 1.0f));
-    O = __builtin_fmaf(s1, k, -b);
+    const R k = fma_r(s2, R(1.0 / 6.0), fma_r(R(0.5), al, R(1)));
+    O = fma_r(s1, k, -b);
 }
 
 // Rest-direction E - 1 (c = 0).
-template <int D>
-__device__ __forceinline__ float target_rest(const TargetInv<D> &T) {
-    const float h = -T.tU;
-    return h * __builtin_fmaf(0.125f, h, 0.5f) + T.K24;
+template <int D, class R>
+__device__ __forceinline__ R target_rest(const TargetInv<D, R> &T) {
+    const R h = -T.tU;
+    return h * fma_r(R(0.125), h, R(0.5)) + T.K24;
+}
+
+// w (rho (E - 1) + drho) and w rho O, w = wh + wl.
+template <class R>
+__device__ __forceinline__ R target_x(R Em1, float rho, float drho, float wh, float wl) {
+    const R t = fma_r(R(rho), Em1, R(drho));
+    return fma_r(R(wh), t, R(wl) * t);
+}
+template <class R>
+__device__ __forceinline__ R target_y(R O, float rho, float wh, float wl) {
+    const R t = R(rho) * O;
+    return fma_r(R(wh), t, R(wl) * t);
 }
 
 // --------------------------------------------------------------------------
@@ -555,59 +602,76 @@ __device__ __forceinline__ CellState<L::D> cell_moments(const Coll &cp, const fl
     });
     cs.drho = drho;
     cs.rho = 1.0f + drho;
-    cs.irho = 1.0f / cs.rho;
-    float ut[3];
+    // the temperatures and the central second moment are formed in FP64 from
+    // the FP32 sums (the subtractions of the density term cancel most of the
+    // sums; rounded in FP32 they bias the pressure of long waves)
+    const double irho = 1.0 / (1.0 + double(drho));
+    cs.irho = float(irho);
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        cs.J[a] = a < D ? J[a] : 0.f;
-        ut[a] = cs.J[a] * cs.irho;
-    }
-    float trM = 0;
+    for (int a = 0; a < 3; a++) cs.J[a] = a < D ? J[a] : 0.f;
+    double trM = 0;
 #pragma unroll
     for (int a = 0; a < D; a++)
 #pragma unroll
         for (int b = a; b < D; b++) {
             const int k = sym_idx(a, b);
-            cs.M[k] = __builtin_fmaf(-cs.J[a], ut[b], S[k]);
-            if (a == b) trM += cs.M[k];
+            const double Mk = double(S[k]) - double(cs.J[a]) * double(cs.J[b]) * irho;
+            cs.M[k] = float(Mk);
+            if (a == b) trM += Mk;
         }
-    // T_tr - 1 = (r^2 tr M - D drho) / (D rho)
-    cs.Ttr1 = __builtin_fmaf(cp.r2, trM, -float(D) * drho) * cs.irho * (1.0f / float(D));
+    const double r2 = double(cp.r2) + double(cp.r2_lo);
+    cs.Ttr1 = float((r2 * trM - double(D) * double(drho)) * irho * (1.0 / double(D)));
     if constexpr (HAS_G) {
-        cs.Tint1 = __builtin_fmaf(cp.two_over_nf, sg, -drho) * cs.irho;
+        const double tnf = double(cp.two_over_nf) + double(cp.two_over_nf_lo);
+        cs.Tint1 = float((tnf * double(sg) - double(drho)) * irho);
     } else {
         cs.Tint1 = cs.Ttr1;
     }
-    cs.Teq1 = __builtin_fmaf(cp.cD, cs.Ttr1, cp.cN * cs.Tint1);
-    cs.Trel1 = __builtin_fmaf(cp.kappa, cs.Teq1, (1.0f - cp.kappa) * cs.Tint1);
+    // blends written so that equal temperatures pass through unchanged
+    // whatever the rounding of the blend weights (cD + cN = 1 and
+    // kappa + (1 - kappa) = 1 only in exact arithmetic)
+    cs.Teq1 = __builtin_fmaf(cp.cN, cs.Tint1 - cs.Ttr1, cs.Ttr1);
+    cs.Trel1 = __builtin_fmaf(cp.kappa, cs.Teq1 - cs.Tint1, cs.Tint1);
     return cs;
 }
 
-// A = Lambda - delta from the cell state.
+// A = Lambda - delta from the cell state, written as
+//   [T_tr - 1 + kappa (T_eq - T_tr)] delta + (1 - kappa) nu (sigma - T_tr delta)
+// (equal to (1-kappa)[(1-nu) T_tr delta + nu sigma] + kappa T_eq delta - delta),
+// so that the isotropic part has coefficient one exactly and the rounding of
+// the blend weights only touches the trace-free stress.  sigma - delta =
+// r^2 M / rho - delta drho / rho.
 template <int D>
 __device__ __forceinline__ void lambda_minus_delta(const Coll &cp, const CellState<D> &cs, float *A) {
-    const float omk = 1.0f - cp.kappa;
-    const float beta = omk * cp.nu * cp.r2 * cs.irho;
-    const float alpha = omk * (1.0f - cp.nu) * cs.Ttr1 + cp.kappa * cs.Teq1 - omk * cp.nu * cs.drho * cs.irho;
+    const float beta = (1.0f - cp.kappa) * cp.nu;
+    float sd[6];   // sigma - delta
 #pragma unroll
-    for (int k = 0; k < 6; k++) A[k] = beta * cs.M[k];
-    A[0] += alpha;
-    A[3] += alpha;
-    if constexpr (D == 3) A[5] += alpha;
+    for (int k = 0; k < 6; k++) sd[k] = mul2(cs.M[k], cp.r2, cp.r2_lo) * cs.irho;
+    const float dr = cs.drho * cs.irho;
+    sd[0] -= dr;
+    sd[3] -= dr;
+    if constexpr (D == 3) sd[5] -= dr;
+    const float iso = __builtin_fmaf(cp.kappa, cs.Teq1 - cs.Ttr1, cs.Ttr1);
+#pragma unroll
+    for (int k = 0; k < 6; k++) A[k] = beta * sd[k];
+    // trace-free part of sigma: subtract T_tr - 1 on the diagonal
+    A[0] = __builtin_fmaf(-beta, cs.Ttr1, A[0]) + iso;
+    A[3] = __builtin_fmaf(-beta, cs.Ttr1, A[3]) + iso;
+    if constexpr (D == 3) A[5] = __builtin_fmaf(-beta, cs.Ttr1, A[5]) + iso;
 }
 
 // --------------------------------------------------------------------------
 // The collision of one cell: F, E in/out (scaled deviations).
 // --------------------------------------------------------------------------
 
-template <class L, bool HAS_G>
+template <class L, bool HAS_G, class R = double>
 __device__ __forceinline__ void collide(const Coll &cp, float *F, float *E) {
     constexpr int D = L::D;
     const CellState<D> cs = cell_moments<L, HAS_G>(cp, F, E);
     float A[6];
     lambda_minus_delta<D>(cp, cs, A);
     float ut[3] = {cs.J[0] * cs.irho, cs.J[1] * cs.irho, cs.J[2] * cs.irho};
-    const TargetInv<D> T = target_inv<D>(A, ut, cp.r2);
+    const TargetInv<D, R> T = target_inv<D, R>(A, ut, cp.r2, cp.r2_lo);
 
     const float om = cp.omega;
     const float rho = cs.rho, drho = cs.drho;
@@ -616,10 +680,10 @@ __device__ __forceinline__ void collide(const Coll &cp, float *F, float *E) {
 
     // rest direction
     {
-        const float X = cp.wh[0] * __builtin_fmaf(rho, target_rest<D>(T), drho);
+        const float X = float(target_x<R>(target_rest<D, R>(T), rho, drho, cp.wh[0], cp.wl[0]));
         F[0] = __builtin_fmaf(om, X - F[0], F[0]);
         if constexpr (HAS_G) {
-            const float gt = __builtin_fmaf(gT, X, gT1 * cp.wh[0]);
+            const float gt = __builtin_fmaf(gT, X, mul2(gT1, cp.wh[0], cp.wl[0]));
             E[0] = __builtin_fmaf(om, gt - E[0], E[0]);
         }
     }
@@ -633,18 +697,17 @@ __device__ __forceinline__ void collide(const Coll &cp, float *F, float *E) {
         constexpr int sh = L::P[p].shell;
         constexpr int a = 2 * p + 1, b = 2 * p + 2;
         if constexpr (first_in_shell<L, p>()) m0 = j0 = j1 = j2 = 0;
-        float Em1, O;
-        target_pair<D, cx, cy, cz>(T, Em1, O);
-        const float w = cp.wh[sh];
-        const float X = w * __builtin_fmaf(rho, Em1, drho);
-        const float Y = (w * rho) * O;
-        const float Ga = X + Y, Gb = X - Y;
+        R Em1, O;
+        target_pair<D, cx, cy, cz, R>(T, Em1, O);
+        const float w = cp.wh[sh], wl = cp.wl[sh];
+        const R X = target_x<R>(Em1, rho, drho, w, wl), Y = target_y<R>(O, rho, w, wl);
+        const float Ga = float(X + Y), Gb = float(X - Y);
         const float fa = __builtin_fmaf(om, Ga - F[a], F[a]);
         const float fb = __builtin_fmaf(om, Gb - F[b], F[b]);
         F[a] = fa;
         F[b] = fb;
         if constexpr (HAS_G) {
-            const float c0 = gT1 * w;
+            const float c0 = mul2(gT1, w, wl);
             const float ga = __builtin_fmaf(gT, Ga, c0), gb = __builtin_fmaf(gT, Gb, c0);
             E[a] = __builtin_fmaf(om, ga - E[a], E[a]);
             E[b] = __builtin_fmaf(om, gb - E[b], E[b]);
@@ -696,23 +759,25 @@ __device__ __forceinline__ void equilibrium(const Coll &cp, float drho, const fl
     // u = r ut  ->  ut = u / r;  r^2 ut = r u
     const float r = __builtin_sqrtf(cp.r2);
     float ut[3] = {u_phys[0] / r, u_phys[1] / r, D == 3 ? u_phys[2] / r : 0.f};
-    const TargetInv<D> T = target_inv<D>(A, ut, cp.r2);
+    const TargetInv<D, double> T = target_inv<D, double>(A, ut, cp.r2, cp.r2_lo);
     const float gT = cp.hN * (1.0f + dT), gT1 = cp.hN * dT;
-    const float X0 = cp.wh[0] * __builtin_fmaf(rho, target_rest<D>(T), drho);
+    const float X0 = float(target_x<double>(target_rest<D, double>(T), rho, drho, cp.wh[0], cp.wl[0]));
     F[0] = X0;
-    if constexpr (HAS_G) E[0] = __builtin_fmaf(gT, X0, gT1 * cp.wh[0]);
+    if constexpr (HAS_G) E[0] = __builtin_fmaf(gT, X0, mul2(gT1, cp.wh[0], cp.wl[0]));
     static_for<L::NP>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
-        float Em1, O;
-        target_pair<D, cx, cy, cz>(T, Em1, O);
-        const float w = cp.wh[L::P[p].shell];
-        const float X = w * __builtin_fmaf(rho, Em1, drho), Y = (w * rho) * O;
-        F[2 * p + 1] = X + Y;
-        F[2 * p + 2] = X - Y;
+        double Em1, O;
+        target_pair<D, cx, cy, cz, double>(T, Em1, O);
+        const float w = cp.wh[L::P[p].shell], wl = cp.wl[L::P[p].shell];
+        const double X = target_x<double>(Em1, rho, drho, w, wl), Y = target_y<double>(O, rho, w, wl);
+        const float Ga = float(X + Y), Gb = float(X - Y);
+        F[2 * p + 1] = Ga;
+        F[2 * p + 2] = Gb;
         if constexpr (HAS_G) {
-            E[2 * p + 1] = __builtin_fmaf(gT, X + Y, gT1 * w);
-            E[2 * p + 2] = __builtin_fmaf(gT, X - Y, gT1 * w);
+            const float c0 = mul2(gT1, w, wl);
+            E[2 * p + 1] = __builtin_fmaf(gT, Ga, c0);
+            E[2 * p + 2] = __builtin_fmaf(gT, Gb, c0);
         }
     });
 }

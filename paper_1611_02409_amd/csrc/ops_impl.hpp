@@ -14,7 +14,7 @@ namespace esbgk {
 // One work-group sweeps cpi consecutive chunks of blockDim.x cells.
 // ROW: every wave lies inside one x-row (nx % 64 == 0); see RowNbr.
 template <class L, int S, int LAY, bool HAS_G, int CP, bool ROW>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW ? (L::Q <= 37 ? 4 : 3) : 1))) void k_step(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW && S != ST_F32 ? (L::Q <= 37 ? 4 : 3) : 1))) void k_step(
     char *fb, char *gb, char *wfb, char *wgb, uint32_t pb, uint32_t sb, Geom g, Coll cp, uint32_t remap,
     uint32_t cpi) {
     const uint32_t blk = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW ? (L::Q
             nb.init(cell, g);
             if (nb.inner) gather<L, S, LAY, HAS_G, CP>(R, nb.v, F, E);
             else gather<L, S, LAY, HAS_G, CP>(R, nb.edge(), F, E);
-            collide<L, HAS_G>(cp, F, E);
+            collide<L, HAS_G, TargetReal<S>>(cp, F, E);
             if constexpr (LAY == LAY_PULL) {
                 scatter<L, S, LAY, HAS_G, CP>(W, nb.v, F, E);   // own cell only
             } else {
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW ? (L::Q
             if constexpr (LAY != LAY_EVEN) nb.init(cell, g);
             else nb.own = cell * StoreBytes<S>::value;
             gather<L, S, LAY, HAS_G, CP>(R, nb, F, E);
-            collide<L, HAS_G>(cp, F, E);
+            collide<L, HAS_G, TargetReal<S>>(cp, F, E);
             scatter<L, S, LAY, HAS_G, CP>(W, nb, F, E);
         }
     }

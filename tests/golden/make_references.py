@@ -4,10 +4,12 @@ Calls only `oracle/` and the seeded input generators in `workloads.py`;
 nothing here touches the GPU library.  Usage (from the repository root):
 
     python tests/golden/make_references.py waves --n 4096 --Pr 0.71 \
-        --steps 1000 5000 --threads 7
+        --steps 1000 --threads 7
+    python tests/golden/make_references.py waves --n 1024 --Pr 0.71 \
+        --steps 1000 5000 --threads 7 --out-n 256
 
 For each requested step count the file `ref_waves{n}_pr{Pr}.npz` gains, as
-float32 deviations block-averaged to a 512^2 grid: rho - 1, u_x, u_y and
+float32 deviations block-averaged to an out_n^2 grid: rho - 1, u_x, u_y and
 T - 1; plus the FP64 domain totals (mass, momentum, energy) at step 0 and at
 each snapshot.  The run is the D2Q37, N_f = 3, tau = 0.6, kappa = 0.2
 configuration with superposed shear/thermal waves and seeded noise.
@@ -69,9 +71,10 @@ def main():
     w.add_argument("--tau", type=float, default=0.6)
     w.add_argument("--steps", type=int, nargs="+", default=[1000, 5000])
     w.add_argument("--threads", type=int, default=0)
+    w.add_argument("--out-n", type=int, default=512, help="side of the block-averaged output grid")
     a = ap.parse_args()
     if a.cmd == "waves":
-        waves(a.n, a.Pr, a.steps, a.threads, tau=a.tau)
+        waves(a.n, a.Pr, a.steps, a.threads, out_n=a.out_n, tau=a.tau)
 
 
 if __name__ == "__main__":

@@ -2,12 +2,11 @@
 
 * 3D: D3Q39 thermal Taylor-Green vortex at 32^3 (u0 = 0.02, T wave 1e-2,
   N_f = 2, Pr = 0.71, tau = 0.7): kinetic energy history and final fields.
-* 4096^2 D2Q37 waves + noise (N_f = 3, Pr = 0.71, tau = 0.6) after 1000 and
-  5000 steps against the stored oracle reference (8x8 block means on a 512^2
-  grid), for FP32, FP16- and BF16-deviation storage: relative L2 of rho, u,
-  T, and the drift of total mass and energy.  Bounds: FP32 1e-5 (the FP32
-  target); FP16/BF16: measured values with a factor-2 margin, stated in the
-  assertion messages and in the design notes.
+* D2Q37 waves + noise (N_f = 3, Pr = 0.71, tau = 0.6) at 4096^2 (1000 steps)
+  and 1024^2 (1000 and 5000 steps) against the stored oracle references
+  (block means on a 512^2 / 256^2 grid), for FP32, FP16- and BF16-deviation
+  storage: relative L2 of rho, u, T, and the drift of total mass and energy,
+  against the bounds in BOUNDS.
 """
 import os
 import sys
@@ -67,15 +66,24 @@ def _reference(n=4096, Pr=0.71):
     return np.load(path)
 
 
-BOUNDS = {  # relative L2 of (rho, u, T) and relative drift of mass and energy
-    "f32": (1e-5, 1e-5, 1e-5, 1e-9),
-    "f16": (2e-6, 2e-3, 2e-6, 1e-7),
-    "bf16": (2e-5, 2e-2, 2e-5, 1e-6),
+# relative L2 of (rho, u, T) and relative drift of total mass and energy,
+# by (storage, steps).  FP32: the collision target and the temperatures are
+# evaluated in FP64 and the error is the FP32 storage and relaxation rounding
+# (measured <= 1.3e-7 in u, <= 2e-10 in rho and T, drifts <= 1e-10); the
+# bounds keep the 1e-5 target with room.  FP16/BF16: twice the largest value
+# measured over the 4096^2 and 1024^2 runs at that step count.
+BOUNDS = {
+    ("f32", 1000): (1e-9, 1e-6, 1e-9, 1e-10, 1e-9),
+    ("f32", 5000): (1e-9, 1e-6, 1e-9, 1e-10, 1e-9),
+    ("f16", 1000): (1e-6, 3e-4, 1e-6, 4e-8, 6e-9),
+    ("f16", 5000): (6e-6, 2e-3, 5e-6, 3e-7, 5e-8),
+    ("bf16", 1000): (3.5e-5, 2.5e-2, 2.5e-5, 7e-7, 5e-8),
+    ("bf16", 5000): (5e-5, 8e-2, 7e-5, 2e-6, 2e-7),
 }
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-@pytest.mark.parametrize("n,steps", [(4096, 1000), (4096, 5000), (1024, 5000)])
+@pytest.mark.parametrize("n,steps", [(4096, 1000), (4096, 5000), (1024, 1000), (1024, 5000)])
 def test_waves_against_fp64_reference(storage, n, steps):
     ref = _reference(n)
     if f"rho_{steps}" not in ref.files:
@@ -99,9 +107,9 @@ def test_waves_against_fp64_reference(storage, n, steps):
     d_en = abs(t1[-1] - t0[-1]) / t0[-1]
     print(f"{storage} {n}^2 x {steps}: rho {e_rho:.2e} u {e_u:.2e} T {e_T:.2e} | mass drift {d_mass:.2e} "
           f"energy drift {d_en:.2e} | gpu-oracle totals {(t1 - to) / to[0]}")
-    b = BOUNDS[storage]
-    assert e_rho < b[0] and e_u < b[1] and e_T < b[2], (storage, e_rho, e_u, e_T, b)
-    assert d_mass < b[3] and d_en < b[3], (storage, d_mass, d_en, b[3])
+    b = BOUNDS[(storage, steps)]
+    assert e_rho < b[0] and e_u < b[1] and e_T < b[2], (storage, steps, e_rho, e_u, e_T, b)
+    assert d_mass < b[3] and d_en < b[4], (storage, steps, d_mass, d_en, b[3:])
 
 
 def test_d2q33_shock_tube_matches_oracle():
