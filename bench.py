@@ -165,14 +165,10 @@ def ingest_counters(fetch_dir, write_dir, ncell=4096 * 4096):
     print(json.dumps(res, indent=1))
 
 
-def cpu_baseline(seconds=12.0):
-    """The FP64 oracle on the host: D2Q37, N_f = 3, 1024^2 periodic, same
-    initial recipe, as many whole steps as fit in about `seconds`."""
+def _oracle_rate(n, threads, seconds, max_steps):
     import oracle
     import workloads
-    threads = min(16, os.cpu_count() or 1)
     oracle.set_threads(threads)
-    n = 1024
     sim = oracle.Sim(2, 37, 3, 0.71, 0.6, (n, n))
     sim.init(*workloads.waves_noise_2d(n))
     steps = 0
@@ -181,13 +177,26 @@ def cpu_baseline(seconds=12.0):
         sim.step(1)
         steps += 1
         el = time.perf_counter() - t0
-        if el > seconds or steps >= 200:
+        if el > seconds or steps >= max_steps:
             break
-    return {"value": round(n * n * steps / el / 1e6, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle, D2Q37 1024x1024 periodic, N_f=3, Pr=0.71, tau=0.6, {steps} steps in {el:.1f} s"}
+    return n * n * steps / el / 1e6, steps, el
 
 
-VARIANTS = ("aa", "f16", "bf16", "d3q39", "batch")
+def cpu_baseline(seconds=12.0):
+    """The FP64 oracle on the host: D2Q37, N_f = 3, 1024^2 periodic, same
+    initial recipe, as many whole steps as fit in about `seconds`, on the
+    host's cores (at most 16, the share of one GPU), and on one thread for a
+    third of that time."""
+    threads = min(16, os.cpu_count() or 1)
+    v, steps, el = _oracle_rate(1024, threads, seconds, 200)
+    v1, steps1, el1 = _oracle_rate(1024, 1, seconds / 3, 200)
+    return {"value": round(v, 3), "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, D2Q37 1024x1024 periodic, N_f=3, Pr=0.71, tau=0.6, {steps} steps in {el:.1f} s "
+                      f"on {threads} threads; {steps1} steps in {el1:.1f} s on 1 thread",
+            "single_thread_value": round(v1, 3)}
+
+
+VARIANTS = ("aa", "pr", "f16", "bf16", "d3q39", "batch")
 
 
 def main():
@@ -199,7 +208,7 @@ def main():
                     help="comma list of variants to time beside the headline: " + ",".join(VARIANTS))
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--batch-steps", type=int, default=200)
+    ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -274,6 +283,17 @@ def main():
             "tile": r["tile"]}
         del r
         torch.cuda.empty_cache()
+    if "pr" in variants:
+        # the same workload at the other two Prandtl numbers (same kernel,
+        # other omega and nu)
+        for pr in (0.5, 2.0):
+            r = time_single(esb, torch, D, Q, Nf, pr, tau, (N, N), "f32", fields, max(50, args.steps // 2),
+                            args.warmup, tune_cache)
+            var[f"d2q37_4096_f32_pr{pr:g}"] = {"mlups": round(r["mlups"], 1),
+                                               "roofline_frac": round(bpl / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                               "streaming": "pull", "tile": r["tile"]}
+            del r
+            torch.cuda.empty_cache()
     for storage in ("f16", "bf16"):
         if storage not in variants:
             continue
@@ -329,7 +349,7 @@ def time_batch(esb, torch, workloads, batch_steps):
     res = {}
 
     def run(name, mode, n):
-        bt.step(n, mode)          # warm-up (captures the graph)
+        bt.step(n if mode != 2 else 20, mode)          # warm-up (captures the graph of n steps)
         torch.cuda.synchronize()
         ms = bt.step_timed(n, mode)
         if bt.status() != 0:
@@ -339,14 +359,14 @@ def time_batch(esb, torch, workloads, batch_steps):
                      "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     for mode, name in ((0, "persistent_graph"), (1, "graph_per_step"), (2, "per_domain_loop")):
-        n = batch_steps if mode != 2 else max(20, batch_steps // 5)
-        log(f"batch {len(doms)} domains, {cells} cells: mode {name}, {n} steps")
-        run(name, mode, n)
+        log(f"batch {len(doms)} domains, {cells} cells: mode {name}, {batch_steps} steps")
+        run(name, mode, batch_steps)
     # the same persistent launch, advancing groups of domains (about 128 MB
     # of storage each) eight steps at a time while they sit in the MALL
     bt.set_tile(256, 0, 8, 128e6)
-    log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {batch_steps} steps")
-    run("persistent_graph_grouped", 0, batch_steps)
+    ng = max(8, batch_steps // 5)
+    log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {ng} steps")
+    run("persistent_graph_grouped", 0, ng)
     res["persistent_graph_grouped"].update(window=8, group_bytes=128e6)
     res["cells"] = cells
     res["domains"] = len(doms)

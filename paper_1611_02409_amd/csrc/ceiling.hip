@@ -10,8 +10,11 @@ namespace {
 
 // Reads 74 planes of each cell from src and writes them to dst (dst == src:
 // in place, as A-A does; another buffer: as two-copy pull does).
+// `lds` bytes of dynamic LDS per work-group only limit how many work-groups
+// share a CU (the pattern streams best at a few waves per SIMD); touch is 0.
 template <int NP>
-__global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_t ncell, uint32_t set_bytes) {
+__global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_t ncell, uint32_t set_bytes, int touch) {
+    extern __shared__ float occupancy_lds[];
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const Sets R(src, src + set_bytes, ncell * 4u, set_bytes);
@@ -22,6 +25,7 @@ __global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_
     float s = 0;
 #pragma unroll
     for (int i = 0; i < NP; i++) s += v[i];
+    if (touch) occupancy_lds[threadIdx.x] = s;
 #pragma unroll
     for (int i = 0; i < NP; i++) st<ST_F32>(v[i] + s * 1e-30f, i < NP / 2 ? W.f : W.g, c * 4u, W.so(i % (NP / 2)));
 }
@@ -31,9 +35,10 @@ __global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_
 
 using namespace esbgk;
 
-// Best of three placements of the pattern: in place on each of two buffers
-// allocated one after the other, and a copy from one to the other.  (Where a
-// buffer lands in HBM moves such streams by a few per cent.)
+// Best of three placements of the pattern (in place on each of two buffers
+// allocated one after the other, and a copy from one to the other: where a
+// buffer lands in HBM moves such streams by a few per cent) and of four
+// occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU).
 extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     clear_error();
     if (cells < 256 || cells > (int64_t)14000000 * 2 || reps < 1 || !gbps) {
@@ -57,20 +62,25 @@ extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     }
     const uint32_t nb = (n + 255) / 256;
     double best = 0;
+    // LDS per CU is 160 KiB: a work-group asking for a bit over 160/(k+1) KiB
+    // leaves room for at most k of them
+    const size_t lds_for[4] = {96 * 1024, 60 * 1024, 44 * 1024, 0};
     for (int pass = 0; pass < 3 && rc == ESBGK_OK; pass++) {
         char *src = p[pass == 1 ? 1 : 0], *dst = p[pass == 0 ? 0 : 1];
-        for (int w = 0; w < 2; w++) k_stream_rw<74><<<nb, 256>>>(src, dst, n, set_bytes);
-        (void)hipEventRecord(e0, nullptr);
-        for (int r = 0; r < reps; r++) k_stream_rw<74><<<nb, 256>>>(src, dst, n, set_bytes);
-        (void)hipEventRecord(e1, nullptr);
-        if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            set_error("stream kernel failed");
-            rc = ESBGK_EDEVICE;
-            break;
+        for (size_t lds : lds_for) {
+            for (int w = 0; w < 2; w++) k_stream_rw<74><<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
+            (void)hipEventRecord(e0, nullptr);
+            for (int r = 0; r < reps; r++) k_stream_rw<74><<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
+            (void)hipEventRecord(e1, nullptr);
+            if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                set_error("stream kernel failed");
+                rc = ESBGK_EDEVICE;
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            best = std::max(best, 2.0 * 2.0 * set_bytes * reps / (ms * 1e-3) / 1e9);
         }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        best = std::max(best, 2.0 * 2.0 * set_bytes * reps / (ms * 1e-3) / 1e9);
     }
     if (rc == ESBGK_OK) *gbps = best;
     if (e0) (void)hipEventDestroy(e0);
