@@ -271,6 +271,10 @@ PULL_CASES = [
     (3, 39, 2, 0.71, 0.7, (12, 10, 8), "f32"),
     (3, 39, 2, 0.71, 0.7, (192, 4, 5), "f32"),
     (2, 33, 1, 1.3, 0.8, (256, 8), "f16"),
+    # rows of whole 256-cell work-groups, one and two per row
+    (2, 37, 3, 0.71, 0.6, (512, 6), "f32"),
+    (2, 37, 1, 0.5, 1.2, (256, 10), "bf16"),
+    (3, 39, 2, 0.71, 0.7, (256, 4, 3), "f32"),
 ]
 
 

@@ -134,3 +134,29 @@ def test_d2q33_shock_tube_matches_oracle():
     er, eu, eT = rel_l2(mg["rho"], mo["rho"]), rel_l2(mg["u"], mo["u"]), rel_l2(mg["T"], mo["T"])
     print(f"shock tube D2Q33: rho {er:.2e} u {eu:.2e} T {eT:.2e}")
     assert er < 1e-5 and eu < 1e-5 and eT < 1e-5
+
+
+@pytest.mark.parametrize("Nf,kappa", [(3, 0.25), (3, 0.9)])
+def test_sound_attenuation_on_gpu(Nf, kappa):
+    """The library's FP32 pressure wave decays at the linearised
+    Navier-Stokes rate with the lattice shear, bulk (kappa) and thermal
+    coefficients, and travels at sqrt(gamma)/r (the closed forms pinned on the
+    oracle in test_oracle_sound)."""
+    from test_oracle_sound import fit_attenuation, predicted_attenuation
+    n, ny, tau, Pr, D = 256, 4, 0.8, 1.0, 2
+    r = esb.lattice_info(2, 37)["r"]
+    cs = np.sqrt((Nf + D + 2) / (Nf + D)) / r
+    lat = esb.Lattice(2, 37, Nf, Pr, tau, (n, ny), kappa=kappa)
+    x = np.tile(np.arange(n, dtype=float), (ny, 1))
+    lat.init_fields(1 + 1e-4 * np.cos(2 * np.pi * x / n), np.zeros((2, ny, n)), np.ones((ny, n)))
+    c = np.cos(2 * np.pi * x / n)
+    amp = []
+    for _ in range(int(6 * n / cs) + 1):
+        m = lat.read_moments()
+        amp.append(2 * np.mean((m["rho"] * m["T"] - 1) * c))
+        lat.step(1)
+    G, w = fit_attenuation(amp, 2 * np.pi / n, cs)
+    Gp = predicted_attenuation(Nf, kappa, tau, Pr, n)
+    print(f"sound N_f={Nf} kappa={kappa}: Gamma {G:.5e} predicted {Gp:.5e} (ratio {G / Gp:.4f}), "
+          f"frequency ratio {w / (cs * 2 * np.pi / n):.5f}")
+    assert abs(G / Gp - 1) < 0.015 and abs(w / (cs * 2 * np.pi / n) - 1) < 0.003
