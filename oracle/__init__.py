@@ -77,6 +77,8 @@ def lib():
         L.orc_sim_steps.restype = ctypes.c_int64
         L.orc_sim_params.argtypes = [ctypes.c_void_p, _c_double_p]
         L.orc_sim_params.restype = None
+        L.orc_sim_set_walls.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p]
+        L.orc_sim_set_walls.restype = ctypes.c_int
         L.orc_collide_cells.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int64, _c_double_p, _c_double_p,
                                         _c_double_p, _c_double_p]
@@ -189,7 +191,8 @@ def cell_moments(D, Q, Nf, fin, gin=None, kappa=0.2):
 
 
 class Sim:
-    """Periodic FP64 simulation (two buffers, collide then pull-stream)."""
+    """FP64 simulation (two buffers, collide then pull-stream), periodic, or
+    with diffusely reflecting walls normal to y (set_walls)."""
 
     def __init__(self, D, Q, Nf, Pr, tau, dims, kappa=0.2, reading="B"):
         self.D, self.Q, self.Nf = D, Q, Nf
@@ -246,6 +249,17 @@ class Sim:
         out = np.zeros(2 + self.D)
         lib().orc_sim_totals(self._h, _p(out))
         return out
+
+    def set_walls(self, bottom, top):
+        """Diffusely reflecting walls normal to y: bottom/top = (u_x, u_y, T)
+        (2D) or (u_x, u_y, u_z, T) (3D) of the wall at low / high y.  The
+        first and last `reach` rows become ghost rows outside the gas."""
+        def w(v):
+            v = list(v)
+            return np.array(v[:-1] + [0.0] * (3 - (len(v) - 1)) + [v[-1]], dtype=np.float64)
+        b, t = w(bottom), w(top)
+        if lib().orc_sim_set_walls(self._h, _p(b), _p(t)) != 0:
+            raise ValueError("oracle: domain too short for walls")
 
     def get_pops(self):
         f = np.zeros(self.Q * self.ncell)

@@ -491,6 +491,12 @@ typedef struct {
     int npop;                      /* 1 (N_f = 0) or 2 */
     double *cur, *nxt;             /* [cell][pop][Q] */
     int64_t steps;
+    /* walls normal to y (0: none): the first and last `reach` rows are
+     * ghost rows outside the gas; see orc_sim_set_walls */
+    int walls, reach;
+    double wall_G[2][ORC_MAXQ];    /* G_i(1, u_w, T_w delta) of the bottom / top wall */
+    double wall_T[2];
+    double wall_in[2];             /* sum over directions entering the gas of |c_y| G_i */
 } orc_sim;
 
 /* periodic wrap of a coordinate displaced by at most a few cells */
@@ -547,13 +553,43 @@ void orc_sim_init(orc_sim *s, const double *rho, const double *u, const double *
     s->steps = 0;
 }
 
+/* Wall density of ghost column (x, z) of wall w (0 bottom, 1 top): the gas
+ * mass streamed into that column's ghost rows during this step (from the
+ * post-collision populations in s->cur) divided by the mass the column
+ * emits per unit density (wall_in).  Diffuse reflection: what reaches the
+ * wall leaves it at the wall's velocity and temperature. */
+static double wall_density(const orc_sim *s, int w, int64_t x, int64_t z) {
+    const int Q = s->B.L.Q, np = s->npop, R = s->reach;
+    const int64_t ny = s->n[1];
+    double in = 0;
+    for (int i = 0; i < Q; i++) {
+        const int cy = s->B.L.c[i][1];
+        if ((w == 0 && cy >= 0) || (w == 1 && cy <= 0)) continue;
+        /* gas rows whose particles with this velocity end in the wall's ghost rows */
+        for (int64_t k = 0; k < (cy < 0 ? -cy : cy); k++) {
+            const int64_t y = w == 0 ? R + k : ny - R - 1 - k;
+            const int64_t yl = y + cy;
+            if ((w == 0 && yl >= R) || (w == 1 && yl < ny - R)) continue;
+            const int64_t src = cell_index(s, x - s->B.L.c[i][0], y, z - s->B.L.c[i][2]);
+            in += s->cur[(size_t)src * np * Q + i];
+        }
+    }
+    return in / s->wall_in[w];
+}
+
 /* One step: collide every cell in place, then pull-stream into the second
- * buffer (f_i(x, t+1) = f_i*(x - c_i, t)), periodic in every axis. */
+ * buffer (f_i(x, t+1) = f_i*(x - c_i, t)), periodic in every axis; with
+ * walls, only the gas rows collide, and a gas cell whose source x - c_i lies
+ * in a ghost row receives the wall's emission rho_w G_i(wall) (g: rho_w
+ * (N_f/2) T_w G_i) with the wall density of the source column. */
 void orc_sim_step(orc_sim *s, int64_t nsteps) {
-    int Q = s->B.L.Q, np = s->npop;
+    int Q = s->B.L.Q, np = s->npop, R = s->walls ? s->reach : 0;
+    const int64_t ny = s->n[1];
     for (int64_t t = 0; t < nsteps; t++) {
         #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < s->ncell; k++) {
+            int64_t y = (k / s->n[0]) % ny;
+            if (y < R || y >= ny - R) continue;
             double *c = s->cur + (size_t)k * np * Q;
             double fo[ORC_MAXQ], go[ORC_MAXQ];
             cell_collide(&s->B, &s->p, c, np == 2 ? c + Q : NULL, fo, go);
@@ -562,16 +598,59 @@ void orc_sim_step(orc_sim *s, int64_t nsteps) {
         }
         #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < s->ncell; k++) {
-            int64_t x = k % s->n[0], y = (k / s->n[0]) % s->n[1], z = k / (s->n[0] * s->n[1]);
+            int64_t x = k % s->n[0], y = (k / s->n[0]) % ny, z = k / (s->n[0] * ny);
             double *dst = s->nxt + (size_t)k * np * Q;
+            if (y < R || y >= ny - R) {
+                /* ghost cell: hold the wall equilibrium at unit density */
+                const int w = y < R ? 0 : 1;
+                for (int i = 0; i < Q; i++) {
+                    dst[i] = s->wall_G[w][i];
+                    if (np == 2) dst[Q + i] = 0.5 * s->p.Nf * s->wall_T[w] * s->wall_G[w][i];
+                }
+                continue;
+            }
             for (int i = 0; i < Q; i++) {
-                int64_t src = cell_index(s, x - s->B.L.c[i][0], y - s->B.L.c[i][1], z - s->B.L.c[i][2]);
+                const int64_t xs = x - s->B.L.c[i][0], ys = y - s->B.L.c[i][1], zs = z - s->B.L.c[i][2];
+                if (ys < R || ys >= ny - R) {
+                    const int w = ys < R ? 0 : 1;
+                    const double rw = wall_density(s, w, wrap(xs, s->n[0]), wrap(zs, s->n[2]));
+                    dst[i] = rw * s->wall_G[w][i];
+                    if (np == 2) dst[Q + i] = rw * 0.5 * s->p.Nf * s->wall_T[w] * s->wall_G[w][i];
+                    continue;
+                }
+                int64_t src = cell_index(s, xs, ys, zs);
                 for (int pp = 0; pp < np; pp++) dst[pp * Q + i] = s->cur[(size_t)src * np * Q + pp * Q + i];
             }
         }
         double *tmp = s->cur; s->cur = s->nxt; s->nxt = tmp;
         s->steps++;
     }
+}
+
+/* Walls normal to y at both ends: rows [0, reach) and [ny - reach, ny) become
+ * ghost rows outside the gas (reach = the largest |c_y| of the lattice), and
+ * each wall reflects diffusely with velocity u_w and temperature T_w:
+ * bottom = {u_x, u_y, u_z, T} of the wall at low y, top likewise.  Periodic
+ * along x (and z).  Returns -1 if the domain has no gas row. */
+int orc_sim_set_walls(orc_sim *s, const double *bottom, const double *top) {
+    int D = s->B.L.D, Q = s->B.L.Q, R = 0;
+    for (int i = 0; i < Q; i++) R = s->B.L.c[i][1] > R ? s->B.L.c[i][1] : R;
+    if (s->n[1] < 2 * R + 1) return -1;
+    const double *wv[2] = {bottom, top};
+    for (int w = 0; w < 2; w++) {
+        double u[3] = {0, 0, 0}, A[9] = {0};
+        for (int a = 0; a < D; a++) { u[a] = wv[w][a]; A[a * D + a] = wv[w][3] - 1.0; }
+        basis_target(&s->B, 1.0, u, A, s->wall_G[w]);
+        s->wall_T[w] = wv[w][3];
+        s->wall_in[w] = 0;
+        for (int i = 0; i < Q; i++) {
+            const int cy = s->B.L.c[i][1];
+            if ((w == 0 && cy > 0) || (w == 1 && cy < 0)) s->wall_in[w] += (cy < 0 ? -cy : cy) * s->wall_G[w][i];
+        }
+    }
+    s->walls = 1;
+    s->reach = R;
+    return 0;
 }
 
 /* Pre-collision moments at the current step: rho, u (D planes), T = T_eq,
@@ -594,12 +673,15 @@ void orc_sim_moments(const orc_sim *s, double *rho, double *u, double *T, double
     }
 }
 
-/* Domain totals in FP64, summed in cell order: {mass, momentum[D], energy},
- * energy = sum (1/2 xi^2 f + g) (Section V, Eq. TransEnergy). */
+/* Domain totals in FP64, summed in cell order over the gas cells: {mass,
+ * momentum[D], energy}, energy = sum (1/2 xi^2 f + g) (Section V, Eq.
+ * TransEnergy). */
 void orc_sim_totals(const orc_sim *s, double *out) {
-    int D = s->B.L.D, Q = s->B.L.Q, np = s->npop;
+    int D = s->B.L.D, Q = s->B.L.Q, np = s->npop, R = s->walls ? s->reach : 0;
     double mass = 0, mom[3] = {0, 0, 0}, en = 0;
     for (int64_t k = 0; k < s->ncell; k++) {
+        const int64_t y = (k / s->n[0]) % s->n[1];
+        if (y < R || y >= s->n[1] - R) continue;   /* gas rows only */
         const double *c = s->cur + (size_t)k * np * Q;
         for (int i = 0; i < Q; i++) {
             double xi2 = 0;
