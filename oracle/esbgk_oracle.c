@@ -600,7 +600,7 @@ void orc_sim_step(orc_sim *s, int64_t nsteps) {
         for (int64_t k = 0; k < s->ncell; k++) {
             int64_t x = k % s->n[0], y = (k / s->n[0]) % ny, z = k / (s->n[0] * ny);
             double *dst = s->nxt + (size_t)k * np * Q;
-            if (y < R || y >= ny - R) {
+            if (s->walls && (y < R || y >= ny - R)) {
                 /* ghost cell: hold the wall equilibrium at unit density */
                 const int w = y < R ? 0 : 1;
                 for (int i = 0; i < Q; i++) {
@@ -611,7 +611,7 @@ void orc_sim_step(orc_sim *s, int64_t nsteps) {
             }
             for (int i = 0; i < Q; i++) {
                 const int64_t xs = x - s->B.L.c[i][0], ys = y - s->B.L.c[i][1], zs = z - s->B.L.c[i][2];
-                if (ys < R || ys >= ny - R) {
+                if (s->walls && (ys < R || ys >= ny - R)) {
                     const int w = ys < R ? 0 : 1;
                     const double rw = wall_density(s, w, wrap(xs, s->n[0]), wrap(zs, s->n[2]));
                     dst[i] = rw * s->wall_G[w][i];
