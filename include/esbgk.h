@@ -144,6 +144,24 @@ int esbgk_init_fields(esbgk_t *h, const double *rho, const double *u, const doub
  * before init. */
 int esbgk_step(esbgk_t *h, int64_t n);
 
+/* Diffusely reflecting walls normal to y, for the thermal Couette flow of
+ * Sec. VI.A (the wall density of the kinetic boundary condition; the
+ * paper's non-equilibrium extrapolation part is not applied).  bottom and
+ * top are {u_x, u_y, u_z, T} of the walls at low and high y (u_z ignored in
+ * 2D; host memory, read during the call).  The first and last `reach` rows
+ * (the largest |c_y| of the lattice) become ghost rows outside the gas;
+ * x (and z) stay periodic.  After every step the library sums, per ghost
+ * column and in FP64, the mass the gas will stream into the wall, and the
+ * wall re-emits it as that density times G(u_w, T_w delta) (f) and
+ * (N_f/2) T_w times that (g); on a stepped state the call does this at
+ * once.  The first step streams the initial state as given.  Only the gas
+ * rows are physical: moments and populations of ghost rows are scratch, and
+ * esbgk_totals returns ESBGK_ESTATE while walls are set.  Both NULL removes
+ * the walls.  Needs ESBGK_PULL storage and ny >= 2 reach + 1 (else
+ * ESBGK_EINVAL); T must be > 0.  The setting is not part of a checkpoint
+ * (the wall emission in the saved ghost rows is).  Synchronous. */
+int esbgk_set_walls(esbgk_t *h, const double *bottom, const double *top);
+
 /* Steps taken since init (or loaded from a checkpoint). */
 int esbgk_step_count(const esbgk_t *h, int64_t *n);
 

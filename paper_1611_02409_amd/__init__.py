@@ -71,6 +71,7 @@ _sig("esbgk_set_kappa", [_vp, ctypes.c_double])
 _sig("esbgk_set_stream", [_vp, _vp])
 _sig("esbgk_init_fields", [_vp, _dp, _dp, _dp])
 _sig("esbgk_step", [_vp, ctypes.c_int64])
+_sig("esbgk_set_walls", [_vp, _dp, _dp])
 _sig("esbgk_step_count", [_vp, _i64p])
 _sig("esbgk_read_moments", [_vp, _dp, _dp, _dp, _dp])
 _sig("esbgk_totals", [_vp, _dp])
@@ -192,6 +193,24 @@ class Lattice:
     def set_stream(self, stream):
         self._stream = stream
         _check(_lib.esbgk_set_stream(self._h, stream.cuda_stream))
+
+    def set_walls(self, bottom, top):
+        """Diffusely reflecting walls at low and high y (the thermal Couette
+        flow of Sec. VI.A): bottom/top = (u_x, u_y, T) in 2D or
+        (u_x, u_y, u_z, T) in 3D; None, None removes them.  The first and last
+        `reach` rows become ghost rows outside the gas; needs streaming="pull"."""
+        if bottom is None and top is None:
+            _check(_lib.esbgk_set_walls(self._h, None, None))
+            return
+
+        def wall(v):
+            v = _f64(v, self.D + 1)
+            out = np.zeros(4)
+            out[:self.D], out[3] = v[:self.D], v[self.D]
+            return out
+
+        b, t = wall(bottom), wall(top)
+        _check(_lib.esbgk_set_walls(self._h, _p(b), _p(t)))
 
     def init_fields(self, rho, u, T):
         n = self.ncell

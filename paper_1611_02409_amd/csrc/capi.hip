@@ -252,11 +252,24 @@ struct esbgk_lattice {
     double *d_partials = nullptr;
     double *d_totals = nullptr;
     uint32_t nchunks = 0;
+    bool walls = false;   // diffusely reflecting walls at low and high y
+    WallSet ws{};
+    // The current state was written by a step (its values are post-collision
+    // and the walls take part in its stream), not laid down by init or
+    // write_populations (which stream into the given pre-collision state,
+    // wall neighbours included).
+    bool from_step = false;
 
+    void apply_walls() { ops->walls(fb(), gb(), pb(), sb(), su.geom, su.coll, ws, has_g(), stream); }
     void launch_step() {
         ops->step(fb(), gb(), wfb(), wgb(), pb(), sb(), su.geom, su.coll, lay(), has_g(), tile[odd() ? 1 : 0],
                   stream);
         steps++;
+        from_step = true;
+        // the new state's ghost rows take the walls' emission, so that every
+        // reader of the state (moments, populations, checkpoints, the next
+        // step) sees what the gas receives in its next stream
+        if (walls) apply_walls();
     }
     // storage of the current state and of the state a step writes (the same
     // storage for A-A; the other copy for two-copy pull)
@@ -468,6 +481,7 @@ int esbgk_init_fields(esbgk_t *h, const double *rho, const double *u, const doub
     ESBGK_HIP(hipMalloc(&tmp.p, host.size() * sizeof(float)));
     ESBGK_HIP(hipMemcpyAsync(tmp.p, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
     h->steps = 0;
+    h->from_step = false;
     h->ops->init(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, (const float *)tmp.p, h->lay(),
                  h->has_g(), h->stream);
     if (int rc = launch_error()) return rc;
@@ -485,6 +499,65 @@ int esbgk_step(esbgk_t *h, int64_t n) {
     }
     for (int64_t k = 0; k < n; k++) h->launch_step();
     return launch_error();
+}
+
+int esbgk_set_walls(esbgk_t *h, const double *bottom, const double *top) {
+    clear_error();
+    if (int rc = check(h)) return rc;
+    if (!bottom && !top) {
+        h->walls = false;
+        return ESBGK_OK;
+    }
+    if (!bottom || !top) {
+        set_error("give both walls (or neither, to remove them)");
+        return ESBGK_EINVAL;
+    }
+    if (h->su.copies != 2) {
+        set_error("walls need the two-copy streaming scheme (storage | ESBGK_PULL)");
+        return ESBGK_EINVAL;
+    }
+    const LatticeConsts &lc = h->su.lc;
+    int R = 0;
+    for (int i = 0; i < h->Q; i++) R = std::max(R, lc.c[i][1]);
+    if (h->dims[1] < 2 * R + 1) {
+        set_error("walls need ny >= %d (%d ghost rows per wall and one gas row)", 2 * R + 1, R);
+        return ESBGK_EINVAL;
+    }
+    const double *wv[2] = {bottom, top};
+    for (int w = 0; w < 2; w++)
+        for (int a = 0; a < 4; a++)
+            if (!std::isfinite(wv[w][a]) || (a == 3 && !(wv[w][3] > 0))) {
+                set_error("wall velocity must be finite and wall temperature finite and > 0");
+                return ESBGK_EINVAL;
+            }
+    WallSet ws{};
+    ws.reach = R;
+    DevTmp tmp;
+    ESBGK_HIP(hipMalloc(&tmp.p, sizeof(double) * 2 * MAX_Q));
+    for (int w = 0; w < 2; w++) {
+        const double u[3] = {wv[w][0], wv[w][1], h->D == 3 ? wv[w][2] : 0.0};
+        h->ops->equilibrium_one(h->su.coll, u, wv[w][3] - 1.0, (double *)tmp.p + w * MAX_Q, h->stream);
+    }
+    if (int rc = launch_error()) return rc;
+    ESBGK_HIP(hipMemcpyAsync(ws.G, tmp.p, sizeof ws.G, hipMemcpyDeviceToHost, h->stream));
+    ESBGK_HIP(hipStreamSynchronize(h->stream));
+    for (int w = 0; w < 2; w++) {
+        ws.T[w] = wv[w][3];
+        for (int i = 0; i < h->Q; i++) {
+            const int cy = lc.c[i][1];
+            const bool into_gas = (w == 0 && cy > 0) || (w == 1 && cy < 0);
+            const bool into_wall = (w == 0 && cy < 0) || (w == 1 && cy > 0);
+            if (into_gas) ws.emit[w] += std::abs(cy) * ws.G[w][i];
+            if (into_wall) ws.rest[w] += std::abs(cy) * lc.wshell[lc.shell_of[i]];
+        }
+    }
+    h->ws = ws;
+    h->walls = true;
+    if (h->initialized && h->from_step) {
+        h->apply_walls();
+        if (int rc = launch_error()) return rc;
+    }
+    return ESBGK_OK;
 }
 
 int esbgk_step_count(const esbgk_t *h, int64_t *n) {
@@ -533,6 +606,10 @@ int esbgk_totals(esbgk_t *h, double *out) {
     if (!out) {
         set_error("out is NULL");
         return ESBGK_EINVAL;
+    }
+    if (h->walls) {
+        set_error("totals cover the whole periodic domain; with walls the ghost rows are not gas");
+        return ESBGK_ESTATE;
     }
     h->ops->plane_sums(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom.ncell, h->Q, h->has_g(), h->d_partials,
                        h->nchunks, h->stream);
@@ -642,6 +719,7 @@ int esbgk_write_populations(esbgk_t *h, const double *f, const double *g) {
     h->ops->write(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->lay(), h->has_g(), (const float *)din.p,
                   h->stream);
     if (int rc = launch_error()) return rc;
+    h->from_step = false;
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->initialized = true;
     return ESBGK_OK;
@@ -651,7 +729,8 @@ int esbgk_write_populations(esbgk_t *h, const double *f, const double *g) {
 namespace {
 struct CkptHeader {
     char magic[8];
-    int32_t version, D, Q, Nf, storage, pad;
+    int32_t version, D, Q, Nf, storage;
+    int32_t flags;   // bit 0: the state was written by a step
     int64_t dims[3];
     int64_t steps;
     double Pr, tau, kappa;
@@ -685,6 +764,7 @@ int esbgk_save(esbgk_t *h, const char *path) {
     hd.storage = h->storage;
     for (int d = 0; d < 3; d++) hd.dims[d] = h->dims[d];
     hd.steps = h->steps;
+    hd.flags = h->from_step ? 1 : 0;
     hd.Pr = h->Pr;
     hd.tau = h->tau;
     hd.kappa = h->kappa;
@@ -749,6 +829,7 @@ int esbgk_load(esbgk_t *h, const char *path) {
     std::memcpy(h->su.prm, prm, sizeof prm);
     h->su.coll = make_coll(h->su.lc, prm, h->D, h->Nf, hd.kappa);
     h->steps = hd.steps;
+    h->from_step = (hd.flags & 1) != 0;
     ESBGK_HIP(hipMemcpyAsync(h->fb(), host.data(), host.size(), hipMemcpyHostToDevice, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->initialized = true;
@@ -855,6 +936,7 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
     ESBGK_HIP(hipMalloc(&save.p, h->su.bytes));
     ESBGK_HIP(hipMemcpyAsync(save.p, h->buf, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
     const int64_t steps0 = h->steps;
+    const bool from_step0 = h->from_step;
     hipEvent_t ev[7];
     for (auto &e : ev) ESBGK_HIP(hipEventCreate(&e));
     double best[2] = {1e30, 1e30};
@@ -902,6 +984,7 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
     ESBGK_HIP(hipMemcpyAsync(h->buf, save.p, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->steps = steps0;
+    h->from_step = from_step0;
     if (rc) return rc;
     h->tile[0] = bestt[0];
     h->tile[1] = bestt[1];

@@ -453,8 +453,8 @@ __device__ __forceinline__ int sym_idx(int a, int b) {
 
 // Target invariants from A (physical, symmetric, 6 slots) and the
 // lattice-unit velocity ut = J/rho; r^2 = r2_hi + r2_lo.
-template <int D, class R>
-__device__ __forceinline__ TargetInv<D, R> target_inv(const float *Af, const float *utf, float r2_hi, float r2_lo) {
+template <int D, class R, class In = float>
+__device__ __forceinline__ TargetInv<D, R> target_inv(const In *Af, const In *utf, float r2_hi, float r2_lo) {
     TargetInv<D, R> T;
     R A[6], ut[3];
 #pragma unroll
@@ -781,6 +781,17 @@ __device__ __forceinline__ void equilibrium(const Coll &cp, float drho, const fl
         }
     });
 }
+
+// Diffusely reflecting walls normal to y (two-copy pull layout).  Rows
+// [0, reach) and [ny - reach, ny) are ghost rows outside the gas.  Per wall
+// (0 bottom, 1 top), in the library's direction order:
+struct WallSet {
+    double G[2][MAX_Q];   // G_i(1, u_w, T_w delta): the wall's emission per unit density
+    double T[2];          // wall temperatures
+    double emit[2];       // sum over gas-bound directions of |c_y| G_i (mass emitted per unit density)
+    double rest[2];       // sum over wall-bound directions of |c_y| w_i (rest part of the mass received)
+    int reach;
+};
 
 // XCD-aware block order: the eight XCDs take blocks round-robin; give XCD k a
 // contiguous run of logical blocks so that neighbouring tiles share its L2.

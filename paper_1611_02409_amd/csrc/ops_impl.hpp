@@ -206,6 +206,99 @@ __global__ __launch_bounds__(256) void k_plane_sums(char *fb, char *gb, uint32_t
     if (threadIdx.x == 0) partials[(uint64_t)plane * nchunks + chunk] = red[0];
 }
 
+// ---------------------------------------------------------------- walls
+// After each step of a domain with walls, on the state it wrote (two-copy
+// pull layout; (fb, gb) is that copy, whose value of direction i at cell p is
+// what p streams along c_i in the next step): one thread per ghost column
+// (x, z) and wall.  It sums, in FP64, the mass the gas will stream into the
+// column's ghost rows (gas cells (x - c_x, y, z - c_z) within |c_y| rows of
+// the wall, wall-bound directions) and divides by the wall's emission per
+// unit density: rho_w.  The column's ghost cells then hold rho_w G_i(wall)
+// (g: rho_w (N_f/2) T_w G_i) in the gas-bound directions, which is what the
+// gas cells read in that stream, and the unit-density wall state in the
+// others.  Diffuse reflection: what a wall receives it re-emits at its
+// velocity and temperature.
+template <class L, int S, bool HAS_G>
+__global__ __launch_bounds__(256) void k_walls(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, Coll cp,
+                                               WallSet ws) {
+    const uint32_t ncol = g.nx * g.nz;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * ncol) return;
+    const int w = idx < ncol ? 0 : 1;
+    const uint32_t col = idx - (w ? ncol : 0);
+    const int x = int(col % g.nx), z = int(col / g.nx);
+    const int nx = int(g.nx), ny = int(g.ny), nz = int(g.nz), R = ws.reach;
+    constexpr uint32_t B = StoreBytes<S>::value;
+    const Sets W(fb, gb, pb, sb);
+    auto at = [&](int xx, int yy, int zz) {
+        xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+        zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+        return uint32_t((zz * ny + yy) * nx + xx) * B;
+    };
+    // mass received: rest part + sum of stored deviations / scale
+    double in = ws.rest[w];
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int sh = L::P[p].shell;
+        static_for<2>([&](auto ss) {
+            constexpr int sgn = decltype(ss)::value == 0 ? 1 : -1;
+            constexpr int cx = sgn * L::P[p].c[0], cy = sgn * L::P[p].c[1], cz = sgn * L::P[p].c[2];
+            constexpr int i = decltype(ss)::value == 0 ? 2 * p + 1 : 2 * p + 2;
+            if constexpr (cy != 0) {
+                if ((w == 0 && cy < 0) || (w == 1 && cy > 0)) {
+                    constexpr int ay = cy < 0 ? -cy : cy;
+                    for (int k = 0; k < ay; k++) {
+                        const int y = w == 0 ? R + k : ny - R - 1 - k;
+                        in += double(ld<S>(W.f, at(x - cx, y, z - cz), W.so(i))) * double(cp.isc[sh]);
+                    }
+                }
+            }
+        });
+    });
+    const double rw = in / ws.emit[w];
+    const double hN = double(cp.hN);
+    for (int k = 0; k < R; k++) {
+        const int y = w == 0 ? k : ny - R + k;
+        const uint32_t o = at(x, y, z);
+        static_for<L::Q>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            constexpr int sh = i == 0 ? 0 : L::P[(i - 1) / 2].shell;
+            constexpr int cy = i == 0 ? 0 : ((i & 1) ? L::P[(i - 1) / 2].c[1] : -L::P[(i - 1) / 2].c[1]);
+            const bool into_gas = (w == 0 && cy > 0) || (w == 1 && cy < 0);
+            const double wi = (double(cp.wh[sh]) + double(cp.wl[sh])) * double(cp.isc[sh]);
+            const double sc = 1.0 / double(cp.isc[sh]);
+            const double G = (into_gas ? rw : 1.0) * ws.G[w][i];
+            st<S>(float((G - wi) * sc), W.f, o, W.so(i));
+            if constexpr (HAS_G) st<S>(float((hN * ws.T[w] * G - hN * wi) * sc), W.g, o, W.so(i));
+        });
+    }
+}
+
+// G_i(1, u, (1 + dT) delta) of one cell in FP64 (the target evaluated as in
+// the collision, at unit density): the walls' emission per unit density.
+template <class L>
+__global__ void k_equilibrium_one(Coll cp, double ux, double uy, double uz, double dT, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    constexpr int D = L::D;
+    const double A[6] = {dT, 0, 0, dT, 0, D == 3 ? dT : 0.0};
+    const double r = __builtin_sqrt(double(cp.r2) + double(cp.r2_lo));
+    const double ut[3] = {ux / r, uy / r, D == 3 ? uz / r : 0.0};
+    const TargetInv<D, double> T = target_inv<D, double, double>(A, ut, cp.r2, cp.r2_lo);
+    auto w_of = [&](int sh) { return (double(cp.wh[sh]) + double(cp.wl[sh])) * double(cp.isc[sh]); };
+    out[0] = w_of(0) + target_x<double>(target_rest<D, double>(T), 1.0f, 0.0f, cp.wh[0], cp.wl[0]) * double(cp.isc[0]);
+    static_for<L::NP>([&](auto pp) {
+        constexpr int p = decltype(pp)::value;
+        constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
+        constexpr int sh = L::P[p].shell;
+        double Em1, O;
+        target_pair<D, cx, cy, cz, double>(T, Em1, O);
+        const double X = target_x<double>(Em1, 1.0f, 0.0f, cp.wh[sh], cp.wl[sh]);
+        const double Y = target_y<double>(O, 1.0f, cp.wh[sh], cp.wl[sh]);
+        out[2 * p + 1] = w_of(sh) + (X + Y) * double(cp.isc[sh]);
+        out[2 * p + 2] = w_of(sh) + (X - Y) * double(cp.isc[sh]);
+    });
+}
+
 // ---------------------------------------------------------------- launchers
 inline uint32_t nblocks(uint64_t n, int block) { return (uint32_t)((n + block - 1) / block); }
 
@@ -288,7 +381,16 @@ struct OpsImpl {
         dim3 grid(nchunks, has_g ? 2 * q : q);
         k_plane_sums<S><<<grid, 256, 0, s>>>(fb, gb, pb, sb, ncell, q, partials);
     }
-    static constexpr Ops ops{&step, &init, &moments, &cells, &write, &plane_sums};
+    static void walls(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, const WallSet &ws,
+                      bool has_g, hipStream_t s) {
+        const uint32_t nb = nblocks(2ull * g.nx * g.nz, 256);
+        if (has_g) k_walls<L, S, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, ws);
+        else k_walls<L, S, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, ws);
+    }
+    static void equilibrium_one(const Coll &c, const double *u, double dT, double *out, hipStream_t s) {
+        k_equilibrium_one<L><<<1, 64, 0, s>>>(c, u[0], u[1], u[2], dT, out);
+    }
+    static constexpr Ops ops{&step, &init, &moments, &cells, &write, &plane_sums, &walls, &equilibrium_one};
 };
 
 }  // namespace esbgk

@@ -80,6 +80,11 @@ struct Ops {
                   hipStream_t s);
     void (*plane_sums)(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, int nplanes_per_set, bool has_g,
                        double *partials, uint32_t nchunks, hipStream_t s);
+    // wall emissions of the current pull-layout copy (see k_walls)
+    void (*walls)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, const WallSet &ws,
+                  bool has_g, hipStream_t s);
+    // G_i(1, u, T delta) of one cell (physical u[3], dT = T - 1) into out[Q] (device, FP64)
+    void (*equilibrium_one)(const Coll &c, const double *u, double dT, double *out, hipStream_t s);
 };
 
 const Ops *get_ops(int D, int Q, int storage);
