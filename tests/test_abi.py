@@ -115,5 +115,6 @@ def test_null_handles_are_rejected(esb):
     lib = esb._lib
     assert lib.esbgk_step(None, 1) == -1
     assert lib.esbgk_totals(None, None) == -1
+    assert lib.esbgk_set_walls(None, None, None) == -1
     lib.esbgk_destroy(None)
     lib.esbgk_batch_destroy(None)

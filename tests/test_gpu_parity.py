@@ -189,6 +189,42 @@ def test_full_size_one_step_sampled(steps0):
     assert ef < 1e-6 and eg < 1e-6
 
 
+# the largest domains one population set allows (4 GiB per set: 29.0M cells
+# in FP32, 58.0M in FP16/BF16 for D2Q37): byte offsets of the last planes
+# come within 1 % of 2^32
+MAX_CASES = [("f32", "aa", 5376), ("f32", "pull", 5376), ("bf16", "pull", 7616)]
+
+
+@pytest.mark.parametrize("storage,streaming,N", MAX_CASES)
+def test_maximum_size_sampled(storage, streaming, N):
+    """One step at sampled cells of the largest allowed square D2Q37 domain
+    (including the last cell and both ends of the last row) equals the
+    oracle's collision of the GPU's own pre-step populations at x - c_i."""
+    D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
+    n = N * N
+    assert 0.99 * 2 ** 32 < n * Q * (4 if storage == "f32" else 2) < 2 ** 32
+    perm, li = perm_to_oracle(D, Q)
+    lat = gpu_run(D, Q, Nf, Pr, tau, (N, N), workloads.waves_noise_2d(N), 3, storage=storage, streaming=streaming)
+    rng = np.random.default_rng(N)
+    cells = np.concatenate([rng.integers(0, n, 40), [0, N - 1, n - 1, n - N, n - N // 2]])
+    nb = neighbourhood((N, N), cells, li["c"])
+    f0, g0 = lat.read_cells(nb.ravel())
+    lat.step(1)
+    f1, g1 = lat.read_cells(cells)
+    inv = np.argsort(perm)
+    fo, go = oracle.collide_cells(D, Q, Nf, Pr, tau, 0.2, f0[:, inv], g0[:, inv])
+    fo = fo[:, perm].reshape(cells.size, Q, Q)
+    go = go[:, perm].reshape(cells.size, Q, Q)
+    diag = (np.arange(cells.size)[:, None], np.arange(Q)[None, :], np.arange(Q)[None, :])
+    ef = float(np.max(np.abs(f1 - fo[diag]) / li["w"]))
+    eg = float(np.max(np.abs(g1 - go[diag]) / li["w"])) / Nf
+    print(f"max size {storage} {streaming} {N}^2: f {ef:.2e} g {eg:.2e}")
+    tol = 1e-6 if storage == "f32" else 1e-4
+    assert ef < tol and eg < tol
+    del lat
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("streaming", ["aa", "pull"])
 def test_save_load_continues_bitwise(tmp_path, streaming):
     dims = (32, 32)
