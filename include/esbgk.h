@@ -42,7 +42,11 @@
  *     rest-state value; ESBGK_F16_DEV and ESBGK_BF16_DEV keep it as an FP16 or
  *     BF16 deviation multiplied by a per-direction power of two near 1/w_i.
  *     Collision arithmetic is FP32 in all modes.  ESBGK_PULL or-ed into the
- *     storage argument selects the two-copy streaming scheme.
+ *     storage argument selects the two-copy streaming scheme.  One direction
+ *     of all cells forms a plane; the Q planes of a population form a set of
+ *     at most 4 GiB (the largest domain: 2^32 / (Q * 4) cells for FP32, and
+ *     for FP16/BF16 with N_f > 0, whose f_i and g_i share one 4-byte element;
+ *     2^32 / (Q * 2) for FP16/BF16 with N_f = 0).
  *   Errors: every int-returning call returns ESBGK_OK (0) or a negative code
  *     below and sets a thread-local message (esbgk_last_error).  No call
  *     throws or aborts.  A failing call leaves the handle usable unless it

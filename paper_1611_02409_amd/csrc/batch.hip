@@ -239,9 +239,8 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
             return rc;
         }
         b->desc[k].kappa = kappa;
-        const uint64_t set = b->su[k].bytes / b->su[k].npop;
         b->f_off[k] = off;
-        b->g_off[k] = b->su[k].npop == 2 ? off + set : 0;
+        b->g_off[k] = b->su[k].npop == 2 ? off + b->su[k].g_off : 0;
         off += b->su[k].bytes;
     }
     b->bytes = off;
@@ -441,7 +440,7 @@ int esbgk_batch_info(const esbgk_batch_t *b, int64_t *cells, double *bytes_per_s
     double by = 0;
     for (int k = 0; k < b->n; k++) {
         c += b->su[k].geom.ncell;
-        by += 2.0 * (double)b->su[k].plane_bytes * b->Q * b->su[k].npop;
+        by += 2.0 * (double)b->su[k].geom.ncell * b->Q * b->su[k].npop * b->su[k].esize;
     }
     if (cells) *cells = c;
     if (bytes_per_step) *bytes_per_step = by;

@@ -71,9 +71,9 @@ __device__ __forceinline__ uint32_t uniform_u32(const uint32_t *p) { return __bu
 template <class L, int S, int CP, bool ODD, bool HAS_G>
 __device__ __forceinline__ void tile_step(char *base, const DomDev &dd, uint32_t cell) {
     if (cell >= dd.geom.ncell) return;
-    Nbr<L, S> nb;
+    Nbr<L, kElemBytes<S, HAS_G>> nb;
     if constexpr (ODD) nb.init(cell, dd.geom);
-    else nb.own = cell * StoreBytes<S>::value;
+    else nb.own = cell * kElemBytes<S, HAS_G>;
     const Sets R(base + dd.f_off, HAS_G ? base + dd.g_off : nullptr, dd.pb, dd.sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
     gather<L, S, ODD, HAS_G, CP>(R, nb, F, E);

@@ -118,19 +118,23 @@ int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, cons
         }
     }
     out.esize = codec == ESBGK_F32 ? 4 : 2;
-    out.plane_bytes = ncell * out.esize;
+    out.npop = Nf > 0 ? 2 : 1;
+    out.paired = codec != ESBGK_F32 && out.npop == 2;
+    const uint64_t ebytes = out.esize * (out.paired ? 2 : 1);
+    out.plane_bytes = ncell * ebytes;
     const uint64_t set_bytes = out.plane_bytes * (uint64_t)Q;
     if (set_bytes >= ((uint64_t)1 << 32)) {
         set_error("one population set would take %llu bytes; the limit is 4 GiB per set (%llu cells for this "
-                  "lattice and storage)",
-                  (unsigned long long)set_bytes, (unsigned long long)((((uint64_t)1 << 32) - 1) / (out.esize * Q)));
+                  "lattice, storage and N_f)",
+                  (unsigned long long)set_bytes, (unsigned long long)((((uint64_t)1 << 32) - 1) / (ebytes * Q)));
         return ESBGK_EUNSUPPORTED;
     }
-    out.npop = Nf > 0 ? 2 : 1;
     // planes are 256-byte aligned inside a set only through the cell count;
     // sets and copies start 256-byte aligned
     out.set_stride = (set_bytes + 255) & ~uint64_t(255);
-    out.copy_bytes = out.set_stride * out.npop;
+    const int nsets = out.paired ? 1 : out.npop;
+    out.g_off = out.npop == 2 ? (out.paired ? out.esize : out.set_stride) : 0;
+    out.copy_bytes = out.set_stride * nsets;
     out.bytes = out.copy_bytes * out.copies;
     out.coll = make_coll(out.lc, out.prm, D, Nf, kappa);
     Geom &g = out.geom;
@@ -275,9 +279,9 @@ struct esbgk_lattice {
     // storage for A-A; the other copy for two-copy pull)
     char *copy(int64_t s) const { return buf + (su.copies == 2 ? (uint64_t)(s & 1) * su.copy_bytes : 0); }
     char *fb() const { return copy(steps); }
-    char *gb() const { return su.npop == 2 ? fb() + su.set_stride : nullptr; }
+    char *gb() const { return su.npop == 2 ? fb() + su.g_off : nullptr; }
     char *wfb() const { return copy(steps + 1); }
-    char *wgb() const { return su.npop == 2 ? wfb() + su.set_stride : nullptr; }
+    char *wgb() const { return su.npop == 2 ? wfb() + su.g_off : nullptr; }
     uint32_t pb() const { return (uint32_t)su.plane_bytes; }
     uint32_t sb() const { return (uint32_t)(su.plane_bytes * (uint64_t)Q); }
     bool odd() const { return (steps & 1) != 0; }
@@ -756,8 +760,8 @@ int esbgk_save(esbgk_t *h, const char *path) {
     ESBGK_HIP(hipMemcpyAsync(host.data(), h->fb(), h->su.copy_bytes, hipMemcpyDeviceToHost, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     CkptHeader hd{};
-    std::memcpy(hd.magic, "ESBGKCK1", 8);
-    hd.version = 1;
+    std::memcpy(hd.magic, "ESBGKCK2", 8);
+    hd.version = 2;
     hd.D = h->D;
     hd.Q = h->Q;
     hd.Nf = h->Nf;
@@ -796,7 +800,7 @@ int esbgk_load(esbgk_t *h, const char *path) {
         return ESBGK_EIO;
     }
     CkptHeader hd{};
-    if (std::fread(&hd, sizeof hd, 1, fp) != 1 || std::memcmp(hd.magic, "ESBGKCK1", 8) != 0) {
+    if (std::fread(&hd, sizeof hd, 1, fp) != 1 || std::memcmp(hd.magic, "ESBGKCK2", 8) != 0) {
         std::fclose(fp);
         set_error("%s is not an esbgk checkpoint", path);
         return ESBGK_EIO;

@@ -53,6 +53,18 @@ struct StoreBytes {
     static constexpr uint32_t value = S == ST_F32 ? 4u : 2u;
 };
 
+// FP16/BF16 storage of a domain with both populations keeps f_i and g_i of a
+// cell side by side in one 4-byte element (f in the low half): one load and
+// one store per direction instead of two, and half as many address streams.
+// FP32 keeps separate f and g sets (its paired 8-byte elements measured
+// slower).
+template <int S, bool HAS_G>
+inline constexpr bool kPaired = S != ST_F32 && HAS_G;
+
+// bytes from one cell's element to the next in a plane
+template <int S, bool HAS_G>
+inline constexpr uint32_t kElemBytes = kPaired<S, HAS_G> ? 2 * StoreBytes<S>::value : StoreBytes<S>::value;
+
 // --------------------------------------------------------------------------
 // Small helpers
 // --------------------------------------------------------------------------
@@ -175,7 +187,41 @@ __device__ __forceinline__ void st(float v, __amdgpu_buffer_rsrc_t r, uint32_t o
     }
 }
 
-// The two population sets of a domain as buffer resources.
+// f and g of one paired 4-byte element (FP16/BF16 storage only).
+template <int S, int CP = 0>
+__device__ __forceinline__ void ld_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff, float &f, float &g) {
+    static_assert(S != ST_F32, "paired elements hold 2-byte values");
+    const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, (int)soff, CP);
+    if constexpr (S == ST_F16) {
+        f = __half2float(__ushort_as_half((unsigned short)(v & 0xffffu)));
+        g = __half2float(__ushort_as_half((unsigned short)(v >> 16)));
+        asm("" : "+v"(f));   // see ld
+        asm("" : "+v"(g));
+    } else {
+        f = __uint_as_float(v << 16);
+        g = __uint_as_float(v & 0xffff0000u);
+    }
+}
+
+template <int S, int CP = 0>
+__device__ __forceinline__ void st_pair(float f, float g, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    static_assert(S != ST_F32, "paired elements hold 2-byte values");
+    uint32_t lo, hi;
+    if constexpr (S == ST_F16) {
+        asm("" : "+v"(f));   // see st
+        asm("" : "+v"(g));
+        lo = __half_as_ushort(__float2half_rn(f));
+        hi = __half_as_ushort(__float2half_rn(g));
+    } else {
+        lo = __bfloat16_as_ushort(__float2bfloat16(f));
+        hi = __bfloat16_as_ushort(__float2bfloat16(g));
+    }
+    __builtin_amdgcn_raw_buffer_store_b32(lo | (hi << 16), r, (int)off, (int)soff, CP);
+}
+
+// The two population sets of a domain as buffer resources.  With paired
+// elements g is the same storage as f shifted by 2 bytes (the high half), so
+// that per-population element accesses work unchanged.
 struct Sets {
     __amdgpu_buffer_rsrc_t f, g;
     uint32_t pb;   // bytes per plane
@@ -196,14 +242,14 @@ struct Off {
     uint32_t s;   // wave-uniform byte offset
 };
 
-template <class L, int S>
+// B: bytes per cell element (kElemBytes).
+template <class L, uint32_t B>
 struct Nbr {
     static constexpr int R = L::REACH;
     uint32_t xo[2 * R + 1], yo[2 * R + 1], zo[L::D == 3 ? 2 * R + 1 : 1];
     uint32_t own;
 
     __device__ __forceinline__ void init(uint32_t cell, const Geom &g) {
-        constexpr uint32_t B = StoreBytes<S>::value;
         uint32_t x, y, z = 0;
         if constexpr (L::D == 2) {
             y = fdiv(cell, g.by_nx);
@@ -251,10 +297,9 @@ struct Nbr {
 // does not touch x = 0 or x = nx - 1 ("inner"), x + k never wraps: the x
 // offset is one register plus the instruction's immediate (k + R) B.  Waves
 // at the two ends of a row wrap x per lane (RowView<.., false>).
-template <class L, int S, bool INNER>
+template <class L, uint32_t B, bool INNER>
 struct RowView {
     static constexpr int R = L::REACH;
-    static constexpr uint32_t B = StoreBytes<S>::value;
     uint32_t xb;                                   // (x - R) B, per lane
     uint32_t nxB;                                  // nx B
     uint32_t yo[2 * R + 1], zo[L::D == 3 ? 2 * R + 1 : 1];   // uniform
@@ -279,14 +324,13 @@ struct RowView {
     __device__ __forceinline__ Off at() const { return {xoff<CX>(), yz<CY, CZ>()}; }
 };
 
-template <class L, int S>
+template <class L, uint32_t B>
 struct RowNbr {
     static constexpr int R = L::REACH;
-    RowView<L, S, true> v;
+    RowView<L, B, true> v;
     bool inner;
 
     __device__ __forceinline__ void init(uint32_t cell, const Geom &g) {
-        constexpr uint32_t B = StoreBytes<S>::value;
         const uint32_t c0 = __builtin_amdgcn_readfirstlane(cell);   // first cell of the wave
         uint32_t y, z = 0, x0;
         if constexpr (L::D == 2) {
@@ -318,8 +362,8 @@ struct RowNbr {
     // the wrapping view; its per-lane base passes through an empty asm so that
     // the wrapped offsets are recomputed where they are used instead of being
     // kept alive across the collision
-    __device__ __forceinline__ RowView<L, S, false> edge() const {
-        RowView<L, S, false> e;
+    __device__ __forceinline__ RowView<L, B, false> edge() const {
+        RowView<L, B, false> e;
         e.xb = v.xb;
         asm volatile("" : "+v"(e.xb));
         e.nxB = v.nxB;
@@ -343,31 +387,32 @@ enum : int { LAY_EVEN = 0, LAY_ODD = 1, LAY_PULL = 2 };
 
 template <class L, int S, int LAY, bool HAS_G, int CP = 0, class NB>
 __device__ __forceinline__ void gather(const Sets &R, const NB &nb, float *F, float *E) {
+    constexpr bool PAIR = kPaired<S, HAS_G>;
+    // f and g of direction i at byte offsets (v, s) of plane `plane`
+    auto load = [&](int i, int plane, uint32_t v, uint32_t s) __attribute__((always_inline)) {
+        if constexpr (PAIR) {
+            ld_pair<S, CP>(R.f, v, R.so(plane) + s, F[i], E[i]);
+        } else {
+            F[i] = ld<S, CP>(R.f, v, R.so(plane) + s);
+            if constexpr (HAS_G) E[i] = ld<S, CP>(R.g, v, R.so(plane) + s);
+        }
+    };
     const Off o = nb.self();
-    F[0] = ld<S, CP>(R.f, o.v, o.s);
-    if constexpr (HAS_G) E[0] = ld<S, CP>(R.g, o.v, o.s);
+    load(0, 0, o.v, o.s);
     static_for<L::NP>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
         constexpr int a = 2 * p + 1, b = 2 * p + 2;   // c_b = -c_a
         if constexpr (LAY == LAY_EVEN) {
-            F[a] = ld<S, CP>(R.f, o.v, R.so(a) + o.s);
-            F[b] = ld<S, CP>(R.f, o.v, R.so(b) + o.s);
-            if constexpr (HAS_G) {
-                E[a] = ld<S, CP>(R.g, o.v, R.so(a) + o.s);
-                E[b] = ld<S, CP>(R.g, o.v, R.so(b) + o.s);
-            }
+            load(a, a, o.v, o.s);
+            load(b, b, o.v, o.s);
         } else {
             // direction a comes from x - c_a, direction b from x + c_a
             constexpr int pa = LAY == LAY_ODD ? b : a, pb = LAY == LAY_ODD ? a : b;
             const Off op = nb.template at<cx, cy, cz>();
             const Off om = nb.template at<-cx, -cy, -cz>();
-            F[a] = ld<S, CP>(R.f, om.v, R.so(pa) + om.s);
-            F[b] = ld<S, CP>(R.f, op.v, R.so(pb) + op.s);
-            if constexpr (HAS_G) {
-                E[a] = ld<S, CP>(R.g, om.v, R.so(pa) + om.s);
-                E[b] = ld<S, CP>(R.g, op.v, R.so(pb) + op.s);
-            }
+            load(a, pa, om.v, om.s);
+            load(b, pb, op.v, op.s);
         }
     });
 }
@@ -379,9 +424,17 @@ __device__ __forceinline__ void gather(const Sets &R, const NB &nb, float *F, fl
 // cache lines), which is LAY_PULL again.
 template <class L, int S, int LAY, bool HAS_G, int CP = 0, class NB>
 __device__ __forceinline__ void scatter(const Sets &R, const NB &nb, const float *F, const float *E) {
+    constexpr bool PAIR = kPaired<S, HAS_G>;
+    auto store = [&](int i, int plane, uint32_t v, uint32_t s) __attribute__((always_inline)) {
+        if constexpr (PAIR) {
+            st_pair<S, CP>(F[i], E[i], R.f, v, R.so(plane) + s);
+        } else {
+            st<S, CP>(F[i], R.f, v, R.so(plane) + s);
+            if constexpr (HAS_G) st<S, CP>(E[i], R.g, v, R.so(plane) + s);
+        }
+    };
     const Off o = nb.self();
-    st<S, CP>(F[0], R.f, o.v, o.s);
-    if constexpr (HAS_G) st<S, CP>(E[0], R.g, o.v, o.s);
+    store(0, 0, o.v, o.s);
     static_for<L::NP>([&](auto pp) {
         constexpr int p = decltype(pp)::value;
         constexpr int cx = L::P[p].c[0], cy = L::P[p].c[1], cz = L::P[p].c[2];
@@ -389,20 +442,12 @@ __device__ __forceinline__ void scatter(const Sets &R, const NB &nb, const float
         if constexpr (LAY == LAY_ODD) {
             const Off op = nb.template at<cx, cy, cz>();
             const Off om = nb.template at<-cx, -cy, -cz>();
-            st<S, CP>(F[a], R.f, op.v, R.so(a) + op.s);
-            st<S, CP>(F[b], R.f, om.v, R.so(b) + om.s);
-            if constexpr (HAS_G) {
-                st<S, CP>(E[a], R.g, op.v, R.so(a) + op.s);
-                st<S, CP>(E[b], R.g, om.v, R.so(b) + om.s);
-            }
+            store(a, a, op.v, op.s);
+            store(b, b, om.v, om.s);
         } else {
             constexpr int pa = LAY == LAY_EVEN ? b : a, pb = LAY == LAY_EVEN ? a : b;
-            st<S, CP>(F[a], R.f, o.v, R.so(pa) + o.s);
-            st<S, CP>(F[b], R.f, o.v, R.so(pb) + o.s);
-            if constexpr (HAS_G) {
-                st<S, CP>(E[a], R.g, o.v, R.so(pa) + o.s);
-                st<S, CP>(E[b], R.g, o.v, R.so(pb) + o.s);
-            }
+            store(a, pa, o.v, o.s);
+            store(b, pb, o.v, o.s);
         }
     });
 }

@@ -26,7 +26,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW && S !=
         if (cell >= g.ncell) return;
         float F[L::Q], E[HAS_G ? L::Q : 1];
         if constexpr (ROW) {
-            RowNbr<L, S> nb;
+            RowNbr<L, kElemBytes<S, HAS_G>> nb;
             nb.init(cell, g);
             if (nb.inner) gather<L, S, LAY, HAS_G, CP>(R, nb.v, F, E);
             else gather<L, S, LAY, HAS_G, CP>(R, nb.edge(), F, E);
@@ -38,9 +38,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW && S !=
                 else scatter<L, S, LAY, HAS_G, CP>(W, nb.edge(), F, E);
             }
         } else {
-            Nbr<L, S> nb;
+            Nbr<L, kElemBytes<S, HAS_G>> nb;
             if constexpr (LAY != LAY_EVEN) nb.init(cell, g);
-            else nb.own = cell * StoreBytes<S>::value;
+            else nb.own = cell * kElemBytes<S, HAS_G>;
             gather<L, S, LAY, HAS_G, CP>(R, nb, F, E);
             collide<L, HAS_G, TargetReal<S>>(cp, F, E);
             scatter<L, S, LAY, HAS_G, CP>(W, nb, F, E);
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(256) void k_init(char *fb, char *gb, uint32_t pb, u
     float F[L::Q], E[HAS_G ? L::Q : 1];
     equilibrium<L, HAS_G>(cp, fields[cell], u, fields[(1 + D) * (uint64_t)ncell + cell], F, E);
     const Sets R(fb, gb, pb, sb);
-    Nbr<L, S> nb;
+    Nbr<L, kElemBytes<S, HAS_G>> nb;
     nb.init(cell, g);
     st<S>(F[0], R.f, nb.own, 0);
     if constexpr (HAS_G) st<S>(E[0], R.g, nb.own, 0);
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_moments(char *fb, char *gb, uint32_t pb
     const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
     constexpr int D = L::D;
-    Nbr<L, S> nb;
+    Nbr<L, kElemBytes<S, HAS_G>> nb;
     nb.init(cell, g);
     const Sets R(fb, gb, pb, sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_cells(char *fb, char *gb, uint32_t pb, 
     if (k >= n) return;
     const uint32_t cell = list ? list[k] : k;
     if (cell >= g.ncell) return;
-    Nbr<L, S> nb;
+    Nbr<L, kElemBytes<S, HAS_G>> nb;
     nb.init(cell, g);
     const Sets R(fb, gb, pb, sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(256) void k_write(char *fb, char *gb, uint32_t pb, 
                                                const float *in) {
     const uint32_t cell = blockIdx.x * blockDim.x + threadIdx.x;
     if (cell >= g.ncell) return;
-    Nbr<L, S> nb;
+    Nbr<L, kElemBytes<S, HAS_G>> nb;
     nb.init(cell, g);
     const uint64_t n = g.ncell;
     const Sets R(fb, gb, pb, sb);
@@ -185,9 +185,10 @@ __global__ __launch_bounds__(256) void k_write(char *fb, char *gb, uint32_t pb, 
 // ---------------------------------------------------------------- plane sums (FP64)
 // partials[plane * nchunks + chunk] = sum over the chunk's cells of the stored
 // value of that plane (raw scaled value, in double).
+// estride: bytes from one cell's element to the next (paired or not).
 template <int S>
 __global__ __launch_bounds__(256) void k_plane_sums(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell,
-                                                    int q, double *partials) {
+                                                    int q, uint32_t estride, double *partials) {
     const uint32_t chunk = blockIdx.x, nchunks = gridDim.x;
     const int plane = blockIdx.y;
     const auto r = set_rsrc(plane < q ? fb : gb, sb);
@@ -195,7 +196,7 @@ __global__ __launch_bounds__(256) void k_plane_sums(char *fb, char *gb, uint32_t
     const uint32_t per = (ncell + nchunks - 1) / nchunks;
     const uint32_t lo = chunk * per, hi = min(ncell, lo + per);
     double s = 0;
-    for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) s += (double)ld<S>(r, c * StoreBytes<S>::value, so);
+    for (uint32_t c = lo + threadIdx.x; c < hi; c += blockDim.x) s += (double)ld<S>(r, c * estride, so);
     __shared__ double red[256];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -228,7 +229,7 @@ __global__ __launch_bounds__(256) void k_walls(char *fb, char *gb, uint32_t pb, 
     const uint32_t col = idx - (w ? ncol : 0);
     const int x = int(col % g.nx), z = int(col / g.nx);
     const int nx = int(g.nx), ny = int(g.ny), nz = int(g.nz), R = ws.reach;
-    constexpr uint32_t B = StoreBytes<S>::value;
+    constexpr uint32_t B = kElemBytes<S, HAS_G>;
     const Sets W(fb, gb, pb, sb);
     auto at = [&](int xx, int yy, int zz) {
         xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
@@ -379,7 +380,8 @@ struct OpsImpl {
     static void plane_sums(char *fb, char *gb, uint32_t pb, uint32_t sb, uint32_t ncell, int q, bool has_g, double *partials,
                            uint32_t nchunks, hipStream_t s) {
         dim3 grid(nchunks, has_g ? 2 * q : q);
-        k_plane_sums<S><<<grid, 256, 0, s>>>(fb, gb, pb, sb, ncell, q, partials);
+        const uint32_t estride = has_g ? kElemBytes<S, true> : kElemBytes<S, false>;
+        k_plane_sums<S><<<grid, 256, 0, s>>>(fb, gb, pb, sb, ncell, q, estride, partials);
     }
     static void walls(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, const WallSet &ws,
                       bool has_g, hipStream_t s) {

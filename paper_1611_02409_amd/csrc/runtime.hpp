@@ -39,9 +39,11 @@ struct DomainSetup {
     int npop;
     int codec;       // ESBGK_F32, ESBGK_F16_DEV or ESBGK_BF16_DEV
     int copies;      // 1: A-A in place; 2: two-copy pull
-    uint32_t esize;
-    uint64_t plane_bytes;
-    uint64_t set_stride;   // bytes from the f set to the g set
+    uint32_t esize;        // bytes per stored value
+    bool paired;           // f_i and g_i side by side in one element (FP16/BF16 storage, N_f > 0)
+    uint64_t plane_bytes;  // one direction's values of all cells (both populations when paired)
+    uint64_t set_stride;   // bytes of a population set (256-byte aligned)
+    uint64_t g_off;        // bytes from f to g: the next set, or 2 within a paired element
     uint64_t copy_bytes;   // bytes of one copy of the state
     uint64_t bytes;        // all population storage
 };

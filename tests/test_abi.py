@@ -96,7 +96,10 @@ def test_storage_bytes(esb):
     assert esb.storage_bytes(3, 39, 2, (256, 256, 256), "bf16") == 2 * 39 * 256 ** 3 * 2
     # two-copy pull keeps two whole copies (each set 256-byte aligned)
     assert esb.storage_bytes(2, 37, 3, (4096, 4096), "f32", "pull") == 2 * n
-    assert esb.storage_bytes(2, 37, 1, (33, 35), "f16", "pull") == 2 * 2 * ((37 * 33 * 35 * 2 + 255) // 256 * 256)
+    assert esb.storage_bytes(2, 37, 1, (33, 35), "f32", "pull") == 2 * 2 * ((37 * 33 * 35 * 4 + 255) // 256 * 256)
+    # FP16/BF16 with both populations: one set of (f_i, g_i) elements
+    assert esb.storage_bytes(2, 37, 1, (33, 35), "f16", "pull") == 2 * ((37 * 33 * 35 * 4 + 255) // 256 * 256)
+    assert esb.storage_bytes(2, 37, 0, (33, 35), "bf16", "pull") == 2 * ((37 * 33 * 35 * 2 + 255) // 256 * 256)
     with pytest.raises(ValueError):
         esb.storage_bytes(2, 37, 3, (64, 64), "f32", "push")
 
