@@ -320,7 +320,7 @@ def main():
         del r, f3
         torch.cuda.empty_cache()
     if "batch" in variants:
-        var["batched_256_d2q37_f32"] = time_batch(esb, torch, workloads, args.batch_steps)
+        var["batched_256_d2q37_f32"] = time_batch(esb, torch, workloads, args.batch_steps, tune_cache)
         torch.cuda.empty_cache()
     if var:
         out["variants"] = var
@@ -338,15 +338,18 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_batch(esb, torch, workloads, batch_steps):
-    """256 independent domains (A-A in place) in the three execution modes,
-    plus the persistent launch advancing MALL-sized domain groups."""
+def time_batch(esb, torch, workloads, batch_steps, tune_cache):
+    """256 independent domains (A-A in place) in the three execution modes
+    with the autotuned launch shape, plus the persistent launch advancing
+    MALL-sized domain groups."""
     doms = workloads.batch_domains(256)
     bt = esb.Batch(2, 37, [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms])
     for k, d in enumerate(doms):
         bt.init_fields(k, *workloads.batch_fields(d))
     cells, bps = bt.info()
-    res = {}
+    block, policy = bt.autotune(cache_path=tune_cache)
+    log(f"batch autotune: block {block}, policy {policy}")
+    res = {"tile": {"block": block, "policy": policy}}
 
     def run(name, mode, n):
         bt.step(n if mode != 2 else 20, mode)          # warm-up (captures the graph of n steps)
@@ -363,7 +366,7 @@ def time_batch(esb, torch, workloads, batch_steps):
         run(name, mode, batch_steps)
     # the same persistent launch, advancing groups of domains (about 128 MB
     # of storage each) eight steps at a time while they sit in the MALL
-    bt.set_tile(256, 0, 8, 128e6)
+    bt.set_tile(block, policy, 8, 128e6)
     ng = max(8, batch_steps // 5)
     log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {ng} steps")
     run("persistent_graph_grouped", 0, ng)

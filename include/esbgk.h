@@ -281,6 +281,19 @@ int esbgk_batch_step(esbgk_batch_t *b, int64_t n, int mode);
  * Results do not depend on any of these. */
 int esbgk_batch_set_tile(esbgk_batch_t *b, int block, int policy, int window, double group_bytes);
 
+/* The batch's autotuner: time the persistent mode (a few steps) for each
+ * work-group size in {128, 256, 512} and both cache policies, on the
+ * batch's own state, put that state (and the step count) back bitwise,
+ * and keep the fastest shape; window and domain grouping stay as set.
+ * With cache_path the choice is looked up first (keyed by lattice,
+ * storage, domain count and log2 of the cell count) and appended when
+ * measured.  budget_ms bounds the timing (<= 0: no bound).  Needs a second
+ * copy of the batch storage on the device while it runs.  Synchronous. */
+int esbgk_batch_autotune(esbgk_batch_t *b, double budget_ms, const char *cache_path);
+
+/* Current work-group size and cache policy (0 or 2) of the batched kernels. */
+int esbgk_batch_get_tile(const esbgk_batch_t *b, int *block, int *policy);
+
 /* esbgk_batch_step bracketed by HIP events on the batch's stream; *ms is
  * the elapsed time.  Synchronous. */
 int esbgk_batch_step_timed(esbgk_batch_t *b, int64_t n, int mode, double *ms);

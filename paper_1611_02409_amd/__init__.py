@@ -308,6 +308,8 @@ _sig("esbgk_batch_info", [_vp, _i64p, _dp])
 _sig("esbgk_batch_read_moments", [_vp, ctypes.c_int, _dp, _dp, _dp, _dp])
 _sig("esbgk_batch_totals", [_vp, ctypes.c_int, _dp])
 _sig("esbgk_batch_read_populations", [_vp, ctypes.c_int, _dp, _dp])
+_sig("esbgk_batch_autotune", [_vp, ctypes.c_double, ctypes.c_char_p])
+_sig("esbgk_batch_get_tile", [_vp, _ip, _ip])
 _sig("esbgk_batch_destroy", [_vp], None)
 
 PERSISTENT, PER_STEP, PER_DOMAIN = 0, 1, 2
@@ -349,6 +351,17 @@ class Batch:
 
     def set_tile(self, block=0, policy=0, window=0, group_bytes=0.0):
         _check(_lib.esbgk_batch_set_tile(self._h, block, policy, window, group_bytes))
+
+    def autotune(self, budget_ms: float = 0.0, cache_path: str | None = None):
+        """Pick (and optionally cache) the fastest work-group size and cache
+        policy of the persistent launch; returns (block, policy)."""
+        _check(_lib.esbgk_batch_autotune(self._h, budget_ms, os.fsencode(cache_path) if cache_path else None))
+        return self.get_tile()
+
+    def get_tile(self):
+        blk, pol = ctypes.c_int(), ctypes.c_int()
+        _check(_lib.esbgk_batch_get_tile(self._h, ctypes.byref(blk), ctypes.byref(pol)))
+        return blk.value, pol.value
 
     def step(self, n=1, mode=PERSISTENT):
         _check(_lib.esbgk_batch_step(self._h, int(n), int(mode)))

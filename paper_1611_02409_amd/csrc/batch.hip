@@ -1,7 +1,12 @@
 // C ABI of batches of independent domains (see include/esbgk.h).
 #include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -549,6 +554,90 @@ int esbgk_batch_read_populations(esbgk_batch_t *b, int k, double *f, double *g) 
             if (g && npop == 2) g[i * n + c] = 0.5 * b->desc[k].N_f * w + (double)host[(Q + i) * n + c];
         }
     }
+    return ESBGK_OK;
+}
+
+int esbgk_batch_autotune(esbgk_batch_t *b, double budget_ms, const char *cache_path) {
+    clear_error();
+    if (int rc = bcheck(b)) return rc;
+    if (int rc = all_inited(b)) return rc;
+    int64_t cells = 0;
+    for (int k = 0; k < b->n; k++) cells += b->su[k].geom.ncell;
+    char key[160];
+    snprintf(key, sizeof key, "batch D%dQ%d st%d n%d log2cells%d", b->D, b->Q, b->storage, b->n,
+             (int)std::floor(std::log2((double)cells)));
+    const int window = (int)b->window;
+    const double gbytes = b->group_bytes;
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        const std::string k0 = std::string(key) + " ";
+        while (std::getline(in, line)) {
+            int blk, pol;
+            if (line.rfind(k0, 0) == 0 && sscanf(line.c_str() + k0.size(), "block %d policy %d", &blk, &pol) == 2 &&
+                esbgk_batch_set_tile(b, blk, pol, window, gbytes) == ESBGK_OK)
+                return ESBGK_OK;
+        }
+        clear_error();
+    }
+    // time the persistent mode over a few steps per candidate, on a copy of
+    // the state that is put back afterwards
+    void *save = nullptr;
+    if (hipMalloc(&save, b->bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("autotune needs a second copy of the batch storage (%llu bytes)", (unsigned long long)b->bytes);
+        return ESBGK_ENOMEM;
+    }
+    const int64_t steps0 = b->steps;
+    int rc = ESBGK_OK;
+    if (hipMemcpyAsync(save, b->buf, b->bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess) rc = ESBGK_EDEVICE;
+    const int old_block = b->block, old_policy = b->policy == 1 ? 2 : 0;
+    int best_block = old_block, best_policy = old_policy;
+    double best = 1e30;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int blk : {256, 512, 128})
+        for (int pol : {0, 2}) {
+            const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (rc || (budget_ms > 0 && el > budget_ms && best < 1e30)) continue;
+            if ((rc = esbgk_batch_set_tile(b, blk, pol, window, gbytes))) break;
+            double ms = 0;
+            if ((rc = esbgk_batch_step(b, 4, 0))) break;                // captures the graph
+            if ((rc = esbgk_batch_step_timed(b, 4, 0, &ms))) break;
+            int status = 0;
+            if ((rc = esbgk_batch_status(b, &status))) break;
+            if (status == 0 && ms < best) {
+                best = ms;
+                best_block = blk;
+                best_policy = pol;
+            }
+        }
+    if (hipMemcpyAsync(b->buf, save, b->bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess && !rc) rc = ESBGK_EDEVICE;
+    if (hipStreamSynchronize(b->stream) != hipSuccess && !rc) rc = ESBGK_EDEVICE;
+    (void)hipFree(save);
+    b->steps = steps0;
+    if (rc) {
+        if (rc == ESBGK_EDEVICE) set_error("device error during batch autotune");
+        (void)esbgk_batch_set_tile(b, old_block, old_policy, window, gbytes);
+        return rc;
+    }
+    if (int r2 = esbgk_batch_set_tile(b, best_block, best_policy, window, gbytes)) return r2;
+    if (cache_path) {
+        FILE *fp = std::fopen(cache_path, "a");
+        if (!fp) {
+            set_error("cannot append to %s", cache_path);
+            return ESBGK_EIO;
+        }
+        std::fprintf(fp, "%s block %d policy %d\n", key, best_block, best_policy);
+        std::fclose(fp);
+    }
+    return ESBGK_OK;
+}
+
+int esbgk_batch_get_tile(const esbgk_batch_t *b, int *block, int *policy) {
+    clear_error();
+    if (int rc = bcheck(b)) return rc;
+    if (block) *block = b->block;
+    if (policy) *policy = b->policy == 1 ? 2 : 0;
     return ESBGK_OK;
 }
 

@@ -141,3 +141,29 @@ def test_init_after_step_is_rejected():
     b.step(1, mode=esb.PER_STEP)
     with pytest.raises(esb.EsbgkError):
         b.init_fields(0, *fields_of(0, DOMS[0]))
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_autotune_restores_state_and_caches(tmp_path, storage):
+    """The batch autotuner times launch shapes on the batch's own state and
+    puts it back bitwise; results after it equal those of an untuned batch;
+    a second call takes the cached shape."""
+    cache = str(tmp_path / "tune.txt")
+    a = make_batch(storage)
+    b = make_batch(storage)
+    a.step(3)
+    b.step(3)
+    before = pops(a)
+    blk, pol = a.autotune(cache_path=cache)
+    assert blk in (128, 256, 512) and pol in (0, 2)
+    assert same(before, pops(a))
+    a.step(5)
+    b.step(5)
+    assert same(pops(a), pops(b))
+    with open(cache) as fh:
+        lines = fh.read().splitlines()
+    assert len(lines) == 1 and lines[0].endswith(f"block {blk} policy {pol}")
+    c = make_batch(storage, block=64)
+    assert c.autotune(cache_path=cache) == (blk, pol)
+    with open(cache) as fh:
+        assert len(fh.read().splitlines()) == 1
