@@ -155,9 +155,9 @@ def ingest_counters(fetch_dir, write_dir, ncell=4096 * 4096):
     res = {"workload": "D2Q37 4096x4096 FP32 f+g", "algorithmic_bytes_per_launch": bpl,
            "stream_kernel_fetch_factor": sf, "stream_kernel_write_factor": sw, "kernels": kernels,
            "kernel_source_hash": kernel_source_hash(),
-           "commands": ["rocprofv3 --pmc FETCH_SIZE -d gpurun_out/pmc_fetch -- python3 bench.py --steps 6 --warmup 2 "
+           "commands": [f"rocprofv3 --pmc FETCH_SIZE -d {fetch_dir} -- python3 bench.py --steps 6 --warmup 2 "
                         "--variants aa --no-cpu",
-                        "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/pmc_write -- python3 bench.py --steps 6 --warmup 2 "
+                        f"rocprofv3 --pmc WRITE_SIZE -d {write_dir} -- python3 bench.py --steps 6 --warmup 2 "
                         "--variants aa --no-cpu",
                         f"python bench.py --ingest-counters {fetch_dir} {write_dir}"]}
     with open(PROFILE_TRAFFIC, "w") as fh:
@@ -216,7 +216,7 @@ def main():
         ingest_counters(*args.ingest_counters)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only (the batched and single-domain paths have no "
+        print("bench.py: the library runs on one GPU only (the batched and single-domain paths have no "
               "multi-GPU mode); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     variants = set() if args.no_variants else {v for v in args.variants.split(",") if v}
