@@ -361,9 +361,20 @@ def time_batch(esb, torch, workloads, batch_steps, tune_cache):
                      "GBs": round(bps * n / (ms * 1e-3) / 1e9, 1),
                      "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
-    for mode, name in ((0, "persistent_graph"), (1, "graph_per_step"), (2, "per_domain_loop")):
+    for mode, name in ((0, "persistent_graph"), (1, "graph_per_step")):
         log(f"batch {len(doms)} domains, {cells} cells: mode {name}, {batch_steps} steps")
         run(name, mode, batch_steps)
+    # the per-domain loop at its own best work-group size (the tuned shape of
+    # the persistent launch need not suit one launch per domain)
+    best = None
+    for blk, pol in sorted({(256, 0), (512, 0), (block, policy)}):
+        bt.set_tile(blk, pol)
+        log(f"batch {len(doms)} domains: mode per_domain_loop, block {blk} policy {pol}, {batch_steps} steps")
+        run("per_domain_loop", 2, batch_steps)
+        r = res.pop("per_domain_loop")
+        if best is None or r["mlups"] > best["mlups"]:
+            best = dict(r, tile={"block": blk, "policy": pol})
+    res["per_domain_loop"] = best
     # the same persistent launch, advancing groups of domains (about 128 MB
     # of storage each) eight steps at a time while they sit in the MALL
     bt.set_tile(block, policy, 8, 128e6)
