@@ -167,6 +167,20 @@ int esbgk_step(esbgk_t *h, int64_t n);
  * (the wall emission in the saved ghost rows is).  Synchronous. */
 int esbgk_set_walls(esbgk_t *h, const double *bottom, const double *top);
 
+/* Open (zero-gradient) ends along x, as for the shock tube of Sec. VI.B
+ * (on != 0; 0 restores periodic x).  The first and last `reach_x` columns
+ * (the largest |c_x| of the lattice) become ghost columns outside the gas:
+ * after every step each ghost cell takes a copy of the stored populations
+ * of the nearest gas cell of its row, so the gas next to an end streams in
+ * the end column's own post-collision populations; on a stepped state the
+ * call does this at once, and the first step streams the initial state as
+ * given.  y (and z) stay periodic.  Only the gas columns are physical;
+ * esbgk_totals returns ESBGK_ESTATE while the ends are open.  Needs
+ * ESBGK_PULL storage, nx >= 2 reach_x + 1 and no walls (else ESBGK_EINVAL;
+ * esbgk_set_walls likewise refuses while the ends are open).  Not part of a
+ * checkpoint.  Synchronous. */
+int esbgk_set_open_x(esbgk_t *h, int on);
+
 /* Steps taken since init (or loaded from a checkpoint). */
 int esbgk_step_count(const esbgk_t *h, int64_t *n);
 

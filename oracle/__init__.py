@@ -79,6 +79,8 @@ def lib():
         L.orc_sim_params.restype = None
         L.orc_sim_set_walls.argtypes = [ctypes.c_void_p, _c_double_p, _c_double_p]
         L.orc_sim_set_walls.restype = ctypes.c_int
+        L.orc_sim_set_open_x.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        L.orc_sim_set_open_x.restype = ctypes.c_int
         L.orc_collide_cells.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int, ctypes.c_int64, _c_double_p, _c_double_p,
                                         _c_double_p, _c_double_p]
@@ -260,6 +262,12 @@ class Sim:
         b, t = w(bottom), w(top)
         if lib().orc_sim_set_walls(self._h, _p(b), _p(t)) != 0:
             raise ValueError("oracle: domain too short for walls")
+
+    def set_open_x(self, on=True):
+        """Open (zero-gradient) ends along x: the first and last `reach_x`
+        columns become ghost columns that repeat the nearest gas column."""
+        if lib().orc_sim_set_open_x(self._h, 1 if on else 0) != 0:
+            raise ValueError("oracle: domain too narrow for open ends, or walls are set")
 
     def get_pops(self):
         f = np.zeros(self.Q * self.ncell)

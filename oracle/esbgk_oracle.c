@@ -497,6 +497,9 @@ typedef struct {
     double wall_G[2][ORC_MAXQ];    /* G_i(1, u_w, T_w delta) of the bottom / top wall */
     double wall_T[2];
     double wall_in[2];             /* sum over directions entering the gas of |c_y| G_i */
+    /* open ends along x (0: periodic): the first and last `reach_x` columns
+     * are ghost columns outside the gas; see orc_sim_set_open_x */
+    int open_x, reach_x;
 } orc_sim;
 
 /* periodic wrap of a coordinate displaced by at most a few cells */
@@ -583,13 +586,13 @@ static double wall_density(const orc_sim *s, int w, int64_t x, int64_t z) {
  * in a ghost row receives the wall's emission rho_w G_i(wall) (g: rho_w
  * (N_f/2) T_w G_i) with the wall density of the source column. */
 void orc_sim_step(orc_sim *s, int64_t nsteps) {
-    int Q = s->B.L.Q, np = s->npop, R = s->walls ? s->reach : 0;
-    const int64_t ny = s->n[1];
+    int Q = s->B.L.Q, np = s->npop, R = s->walls ? s->reach : 0, RX = s->open_x ? s->reach_x : 0;
+    const int64_t nx = s->n[0], ny = s->n[1];
     for (int64_t t = 0; t < nsteps; t++) {
         #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < s->ncell; k++) {
-            int64_t y = (k / s->n[0]) % ny;
-            if (y < R || y >= ny - R) continue;
+            int64_t x = k % nx, y = (k / nx) % ny;
+            if (y < R || y >= ny - R || x < RX || x >= nx - RX) continue;
             double *c = s->cur + (size_t)k * np * Q;
             double fo[ORC_MAXQ], go[ORC_MAXQ];
             cell_collide(&s->B, &s->p, c, np == 2 ? c + Q : NULL, fo, go);
@@ -609,8 +612,13 @@ void orc_sim_step(orc_sim *s, int64_t nsteps) {
                 }
                 continue;
             }
+            if (s->open_x && (x < RX || x >= nx - RX)) continue;   /* ghost column: filled below */
             for (int i = 0; i < Q; i++) {
-                const int64_t xs = x - s->B.L.c[i][0], ys = y - s->B.L.c[i][1], zs = z - s->B.L.c[i][2];
+                int64_t xs = x - s->B.L.c[i][0];
+                const int64_t ys = y - s->B.L.c[i][1], zs = z - s->B.L.c[i][2];
+                /* open ends: a source in a ghost column is the nearest gas
+                 * column of the same row (zero gradient along x) */
+                if (s->open_x) xs = xs < RX ? RX : (xs >= nx - RX ? nx - RX - 1 : xs);
                 if (s->walls && (ys < R || ys >= ny - R)) {
                     const int w = ys < R ? 0 : 1;
                     const double rw = wall_density(s, w, wrap(xs, s->n[0]), wrap(zs, s->n[2]));
@@ -620,6 +628,16 @@ void orc_sim_step(orc_sim *s, int64_t nsteps) {
                 }
                 int64_t src = cell_index(s, xs, ys, zs);
                 for (int pp = 0; pp < np; pp++) dst[pp * Q + i] = s->cur[(size_t)src * np * Q + pp * Q + i];
+            }
+        }
+        if (s->open_x) {
+            /* ghost columns show the nearest gas column (read-outs only) */
+            #pragma omp parallel for schedule(static)
+            for (int64_t k = 0; k < s->ncell; k++) {
+                const int64_t x = k % nx;
+                if (x >= RX && x < nx - RX) continue;
+                const int64_t src = k - x + (x < RX ? RX : nx - RX - 1);
+                memcpy(s->nxt + (size_t)k * np * Q, s->nxt + (size_t)src * np * Q, sizeof(double) * np * Q);
             }
         }
         double *tmp = s->cur; s->cur = s->nxt; s->nxt = tmp;
@@ -635,7 +653,7 @@ void orc_sim_step(orc_sim *s, int64_t nsteps) {
 int orc_sim_set_walls(orc_sim *s, const double *bottom, const double *top) {
     int D = s->B.L.D, Q = s->B.L.Q, R = 0;
     for (int i = 0; i < Q; i++) R = s->B.L.c[i][1] > R ? s->B.L.c[i][1] : R;
-    if (s->n[1] < 2 * R + 1) return -1;
+    if (s->n[1] < 2 * R + 1 || s->open_x) return -1;
     const double *wv[2] = {bottom, top};
     for (int w = 0; w < 2; w++) {
         double u[3] = {0, 0, 0}, A[9] = {0};
@@ -650,6 +668,22 @@ int orc_sim_set_walls(orc_sim *s, const double *bottom, const double *top) {
     }
     s->walls = 1;
     s->reach = R;
+    return 0;
+}
+
+/* Open (zero-gradient) ends along x, as in the shock tube of Sec. VI.B:
+ * columns [0, reach_x) and [nx - reach_x, nx) become ghost columns outside
+ * the gas (reach_x = the largest |c_x| of the lattice); a gas cell whose
+ * stream source lies in a ghost column receives the post-collision value of
+ * the nearest gas column of the same row.  on = 0 restores periodic x.
+ * Returns -1 if the domain has no gas column or if walls are set. */
+int orc_sim_set_open_x(orc_sim *s, int on) {
+    if (!on) { s->open_x = 0; return 0; }
+    int R = 0;
+    for (int i = 0; i < s->B.L.Q; i++) R = s->B.L.c[i][0] > R ? s->B.L.c[i][0] : R;
+    if (s->n[0] < 2 * R + 1 || s->walls) return -1;
+    s->open_x = 1;
+    s->reach_x = R;
     return 0;
 }
 

@@ -72,6 +72,7 @@ _sig("esbgk_set_stream", [_vp, _vp])
 _sig("esbgk_init_fields", [_vp, _dp, _dp, _dp])
 _sig("esbgk_step", [_vp, ctypes.c_int64])
 _sig("esbgk_set_walls", [_vp, _dp, _dp])
+_sig("esbgk_set_open_x", [_vp, ctypes.c_int])
 _sig("esbgk_step_count", [_vp, _i64p])
 _sig("esbgk_read_moments", [_vp, _dp, _dp, _dp, _dp])
 _sig("esbgk_totals", [_vp, _dp])
@@ -211,6 +212,12 @@ class Lattice:
 
         b, t = wall(bottom), wall(top)
         _check(_lib.esbgk_set_walls(self._h, _p(b), _p(t)))
+
+    def set_open_x(self, on: bool = True):
+        """Open (zero-gradient) ends along x (the shock tube of Sec. VI.B): the
+        first and last `reach_x` columns become ghost columns repeating the
+        nearest gas column; needs streaming="pull"."""
+        _check(_lib.esbgk_set_open_x(self._h, 1 if on else 0))
 
     def init_fields(self, rho, u, T):
         n = self.ncell

@@ -258,6 +258,8 @@ struct esbgk_lattice {
     uint32_t nchunks = 0;
     bool walls = false;   // diffusely reflecting walls at low and high y
     WallSet ws{};
+    bool open_x = false;  // zero-gradient ends along x
+    uint32_t rx = 0;      // ghost columns per end
     // The current state was written by a step (its values are post-collision
     // and the walls take part in its stream), not laid down by init or
     // write_populations (which stream into the given pre-collision state,
@@ -265,6 +267,7 @@ struct esbgk_lattice {
     bool from_step = false;
 
     void apply_walls() { ops->walls(fb(), gb(), pb(), sb(), su.geom, su.coll, ws, has_g(), stream); }
+    void apply_open_x() { ops->open_x(fb(), gb(), pb(), sb(), su.geom, rx, has_g(), stream); }
     void launch_step() {
         ops->step(fb(), gb(), wfb(), wgb(), pb(), sb(), su.geom, su.coll, lay(), has_g(), tile[odd() ? 1 : 0],
                   stream);
@@ -274,6 +277,7 @@ struct esbgk_lattice {
         // reader of the state (moments, populations, checkpoints, the next
         // step) sees what the gas receives in its next stream
         if (walls) apply_walls();
+        if (open_x) apply_open_x();
     }
     // storage of the current state and of the state a step writes (the same
     // storage for A-A; the other copy for two-copy pull)
@@ -520,6 +524,10 @@ int esbgk_set_walls(esbgk_t *h, const double *bottom, const double *top) {
         set_error("walls need the two-copy streaming scheme (storage | ESBGK_PULL)");
         return ESBGK_EINVAL;
     }
+    if (h->open_x) {
+        set_error("walls and open x ends cannot be combined");
+        return ESBGK_EINVAL;
+    }
     const LatticeConsts &lc = h->su.lc;
     int R = 0;
     for (int i = 0; i < h->Q; i++) R = std::max(R, lc.c[i][1]);
@@ -559,6 +567,36 @@ int esbgk_set_walls(esbgk_t *h, const double *bottom, const double *top) {
     h->walls = true;
     if (h->initialized && h->from_step) {
         h->apply_walls();
+        if (int rc = launch_error()) return rc;
+    }
+    return ESBGK_OK;
+}
+
+int esbgk_set_open_x(esbgk_t *h, int on) {
+    clear_error();
+    if (int rc = check(h)) return rc;
+    if (!on) {
+        h->open_x = false;
+        return ESBGK_OK;
+    }
+    if (h->su.copies != 2) {
+        set_error("open ends need the two-copy streaming scheme (storage | ESBGK_PULL)");
+        return ESBGK_EINVAL;
+    }
+    if (h->walls) {
+        set_error("walls and open x ends cannot be combined");
+        return ESBGK_EINVAL;
+    }
+    int R = 0;
+    for (int i = 0; i < h->Q; i++) R = std::max(R, h->su.lc.c[i][0]);
+    if (h->dims[0] < 2 * R + 1) {
+        set_error("open ends need nx >= %d (%d ghost columns per end and one gas column)", 2 * R + 1, R);
+        return ESBGK_EINVAL;
+    }
+    h->rx = (uint32_t)R;
+    h->open_x = true;
+    if (h->initialized && h->from_step) {
+        h->apply_open_x();
         if (int rc = launch_error()) return rc;
     }
     return ESBGK_OK;
@@ -611,8 +649,8 @@ int esbgk_totals(esbgk_t *h, double *out) {
         set_error("out is NULL");
         return ESBGK_EINVAL;
     }
-    if (h->walls) {
-        set_error("totals cover the whole periodic domain; with walls the ghost rows are not gas");
+    if (h->walls || h->open_x) {
+        set_error("totals cover the whole periodic domain; with walls or open ends the ghost cells are not gas");
         return ESBGK_ESTATE;
     }
     h->ops->plane_sums(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom.ncell, h->Q, h->has_g(), h->d_partials,

@@ -275,6 +275,41 @@ __global__ __launch_bounds__(256) void k_walls(char *fb, char *gb, uint32_t pb, 
     }
 }
 
+// Open (zero-gradient) ends along x, after each step of a domain with open
+// ends (two-copy pull layout; (fb, gb) is the copy the step wrote): the
+// first and last rx columns are ghost columns, and every ghost cell takes a
+// raw copy of all stored values of the nearest gas cell of its row (x = rx
+// or nx - rx - 1).  The gas cells next to an end then stream in the
+// post-collision populations of the end column, as if the gas continued
+// unchanged past it.  One thread per ghost cell.
+template <class L, int S, bool HAS_G>
+__global__ __launch_bounds__(256) void k_open_x(char *fb, char *gb, uint32_t pb, uint32_t sb, Geom g, uint32_t rx) {
+    const uint32_t nrow = g.ny * g.nz;
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= 2 * rx * nrow) return;
+    const uint32_t row = idx / (2 * rx), k = idx % (2 * rx);
+    const bool right = k >= rx;
+    const uint32_t x = right ? g.nx - 2 * rx + k : k;
+    const uint32_t xs = right ? g.nx - rx - 1 : rx;
+    constexpr uint32_t B = kElemBytes<S, HAS_G>;
+    const uint32_t dst = (row * g.nx + x) * B, src = (row * g.nx + xs) * B;
+    auto copy_set = [&](char *base) {
+        const auto r = set_rsrc(base, sb);
+#pragma unroll
+        for (int i = 0; i < L::Q; i++) {
+            const uint32_t so = uint32_t(i) * pb;
+            if constexpr (B == 4)
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_amdgcn_raw_buffer_load_b32(r, (int)src, (int)so, 0), r,
+                                                      (int)dst, (int)so, 0);
+            else
+                __builtin_amdgcn_raw_buffer_store_b16(__builtin_amdgcn_raw_buffer_load_b16(r, (int)src, (int)so, 0), r,
+                                                      (int)dst, (int)so, 0);
+        }
+    };
+    copy_set(fb);
+    if constexpr (HAS_G && !kPaired<S, HAS_G>) copy_set(gb);   // paired elements carry g already
+}
+
 // G_i(1, u, (1 + dT) delta) of one cell in FP64 (the target evaluated as in
 // the collision, at unit density): the walls' emission per unit density.
 template <class L>
@@ -389,10 +424,16 @@ struct OpsImpl {
         if (has_g) k_walls<L, S, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, ws);
         else k_walls<L, S, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, c, ws);
     }
+    static void open_x(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, uint32_t rx, bool has_g,
+                       hipStream_t s) {
+        const uint32_t nb = nblocks(2ull * rx * g.ny * g.nz, 256);
+        if (has_g) k_open_x<L, S, true><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, rx);
+        else k_open_x<L, S, false><<<nb, 256, 0, s>>>(fb, gb, pb, sb, g, rx);
+    }
     static void equilibrium_one(const Coll &c, const double *u, double dT, double *out, hipStream_t s) {
         k_equilibrium_one<L><<<1, 64, 0, s>>>(c, u[0], u[1], u[2], dT, out);
     }
-    static constexpr Ops ops{&step, &init, &moments, &cells, &write, &plane_sums, &walls, &equilibrium_one};
+    static constexpr Ops ops{&step, &init, &moments, &cells, &write, &plane_sums, &walls, &equilibrium_one, &open_x};
 };
 
 }  // namespace esbgk

@@ -87,6 +87,9 @@ struct Ops {
                   bool has_g, hipStream_t s);
     // G_i(1, u, T delta) of one cell (physical u[3], dT = T - 1) into out[Q] (device, FP64)
     void (*equilibrium_one)(const Coll &c, const double *u, double dT, double *out, hipStream_t s);
+    // open x ends of the current pull-layout copy (see k_open_x)
+    void (*open_x)(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, uint32_t rx, bool has_g,
+                   hipStream_t s);
 };
 
 const Ops *get_ops(int D, int Q, int storage);

@@ -86,3 +86,62 @@ def test_d2q33_shock_tube_matches_exact_solution():
     k = np.argmax((xs > 650) & (rho < 0.5 * (rs + 1.0)))
     Sx = (rs * us) / (rs - 1.0)
     assert abs(xs[k] - (499.5 + Sx * steps / r)) < 3.0
+
+
+def open_tube(steps_list, threads=4, open_x=True):
+    """The shock tube with the paper's open ends: 1000 gas columns between
+    zero-gradient ends (4 ghost columns each for D2Q33), one row."""
+    prev = oracle.set_threads(0)
+    oracle.set_threads(threads)
+    try:
+        RX, L = 4, 1000
+        nx = L + 2 * RX
+        sim = oracle.Sim(2, 33, 3, 0.71, 2 / 3, (nx, 1))
+        x = np.arange(nx, dtype=float)[None, :] - RX
+        sim.init(np.where(x < 500, 4.0, 1.0), np.zeros((2, 1, nx)), np.ones((1, nx)))
+        if open_x:
+            sim.set_open_x(True)
+        out = []
+        for s in steps_list:
+            sim.step(s - sim.steps)
+            m = sim.moments()
+            out.append((s, m["rho"][0, RX:nx - RX], m["u"][0][0, RX:nx - RX]))
+        return out
+    finally:
+        oracle.set_threads(prev)
+
+
+def l1_against_exact(steps, rho, u):
+    r = oracle.Lattice(2, 33).r
+    xs = np.arange(1000, dtype=float)
+    re, ue, _ = riemann.sample(LEFT, RIGHT, G, (xs - 499.5) * r / steps)
+    return np.abs(rho - re).sum() / re.sum(), np.abs(u - ue).sum() / np.abs(ue).sum()
+
+
+def test_open_ends_keep_a_uniform_state():
+    """Zero-gradient ends continue a uniform moving equilibrium exactly."""
+    for Q in (33, 37):
+        nx, ny = 24, 9
+        sim = oracle.Sim(2, Q, 3, 0.71, 0.8, (nx, ny))
+        sim.init(np.full((ny, nx), 1.2), np.stack([np.full((ny, nx), 0.1), np.full((ny, nx), -0.05)]),
+                 np.full((ny, nx), 1.05))
+        sim.set_open_x(True)
+        sim.step(30)
+        m = sim.moments()
+        assert np.max(np.abs(m["rho"] / 1.2 - 1)) < 1e-13 and np.max(np.abs(m["T"] / 1.05 - 1)) < 1e-13
+        assert np.max(np.abs(m["u"][0] - 0.1)) < 1e-13 and np.max(np.abs(m["u"][1] + 0.05)) < 1e-13
+
+
+def test_open_ends_let_the_waves_leave():
+    """The whole 1000-cell tube with open ends follows the exact solution of
+    the infinite tube at t ~ 0.15 (174 steps) and still after the shock
+    (~290 steps) and the rarefaction head (~470 steps) have reached the
+    ends (500 steps): little is reflected.  A periodic tube of the same
+    length does not (its wrap is a second interface)."""
+    for steps, rho, u in open_tube([174, 500]):
+        e_rho, e_u = l1_against_exact(steps, rho, u)
+        print(f"open tube {steps} steps: L1 rho {e_rho:.3e} u {e_u:.3e}")
+        assert e_rho < 0.02 and e_u < 0.04, (steps, e_rho, e_u)
+    (steps, rho, u), = open_tube([500], open_x=False)
+    e_rho, e_u = l1_against_exact(steps, rho, u)
+    assert e_rho > 0.3 and e_u > 0.5
