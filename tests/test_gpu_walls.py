@@ -153,7 +153,7 @@ def test_wall_errors():
     with pytest.raises(RuntimeError, match="temperature"):
         lat.set_walls((0.0, 0.0, 0.0), (0.1, 0.0, 1.0))
     lat.set_walls((0.0, 0.0, 1.0), (0.1, 0.0, 1.0))
-    with pytest.raises(RuntimeError, match="ghost rows"):
+    with pytest.raises(RuntimeError, match="ghost cells"):
         lat.totals()
     lat.step(3)
     lat.set_walls(None, None)
