@@ -33,10 +33,17 @@ PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_d2q37_f32_4096_traffic.
 
 
 def kernel_source_hash() -> str:
+    """Hash of the step kernels' source with comments and blank space
+    removed, so that a traffic summary stays valid across comment edits and
+    is dropped when the code changes."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hpp", "ops_impl.hpp"):
-        with open(os.path.join(ROOT, "paper_1611_02409_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1611_02409_amd", "csrc", f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -7,7 +7,9 @@
 //     F_i = s_i (f_i - w_i),     E_i = s_i (g_i - w_i N_f/2)
 // (rho0 = T0 = 1), in FP32, FP16 or BF16.  Scaling by a power of two is exact,
 // so FP32 results equal those of unscaled deviations; in FP16/BF16 it keeps
-// the small-weight directions in the normal range.
+// the small-weight directions in the normal range.  FP16/BF16 domains with
+// both populations keep F_i and E_i side by side in one 4-byte element of a
+// single set (kPaired).
 //
 // Streaming uses the A-A pattern in place: after an even number of steps
 // f_i(x) sits at (x, plane i); after an odd number it sits at
@@ -15,7 +17,10 @@
 // writes plane opp(i); the odd kernel reads (x - c, plane -c) and (x + c,
 // plane +c) and writes the same two locations with the post-collision values
 // of +c and -c.  Each thread reads and writes exactly the same set of
-// locations, so the update is race-free without a second buffer.
+// locations, so the update is race-free without a second buffer.  The
+// two-copy pull scheme (LAY_PULL) reads (x - c_i, plane i) of one copy and
+// writes (x, plane i) of the other: the same arithmetic on the same values,
+// with whole aligned cache lines stored.
 //
 // The collision (Section V of the paper) per cell, in FP32 registers:
 //   moments rho, j, second moment -> u, sigma, T_tr, T_int, T_eq, T_rel;
