@@ -146,7 +146,12 @@ int esbgk_set_stream(esbgk_t *h, void *hip_stream);
 int esbgk_init_fields(esbgk_t *h, const double *rho, const double *u, const double *T);
 
 /* Enqueue n >= 0 collide-and-stream steps (asynchronous).  ESBGK_ESTATE
- * before init. */
+ * before init.  The call only launches kernels on the handle's stream (no
+ * allocation, copy or memset), so it may be captured into a HIP graph on
+ * that stream; the handle's step counter, which selects the storage layout
+ * for later calls, advances at capture and not at replay, so a captured
+ * sequence should hold an even number of steps (the layout it ends in is
+ * then the one it starts from). */
 int esbgk_step(esbgk_t *h, int64_t n);
 
 /* Diffusely reflecting walls normal to y, for the thermal Couette flow of
