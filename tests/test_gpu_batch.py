@@ -167,3 +167,37 @@ def test_autotune_restores_state_and_caches(tmp_path, storage):
     assert c.autotune(cache_path=cache) == (blk, pol)
     with open(cache) as fh:
         assert len(fh.read().splitlines()) == 1
+
+
+# other lattices in the batch: (D, Q, domains)
+OTHER = [
+    (3, 39, [dict(dims=(12, 10, 8), Nf=2, Pr=0.71, tau=0.7), dict(dims=(64, 4, 5), Nf=0, Pr=1.5, tau=0.9),
+             dict(dims=(9, 7, 11), Nf=3, Pr=0.8, tau=1.1)]),
+    (2, 33, [dict(dims=(40, 24), Nf=3, Pr=0.71, tau=2 / 3), dict(dims=(128, 6), Nf=1, Pr=1.3, tau=0.8),
+             dict(dims=(17, 29), Nf=0, Pr=0.9, tau=0.7)]),
+]
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("D,Q,doms", OTHER, ids=["D3Q39", "D2Q33"])
+def test_other_lattices_batch_equals_single(D, Q, doms, storage):
+    """D3Q39 and D2Q33 domains in the batch: every mode bitwise equals
+    single-domain runs of the same domains."""
+    nsteps = 5
+    res = {}
+    for mode in (esb.PER_DOMAIN, esb.PER_STEP, esb.PERSISTENT):
+        b = esb.Batch(D, Q, doms, storage=storage)
+        for k, d in enumerate(doms):
+            b.init_fields(k, *workloads.random_state(d["dims"], seed=200 + k))
+        b.step(nsteps, mode=mode)
+        assert b.status() == 0
+        res[mode] = [b.read_populations(k) for k in range(len(doms))]
+    for k, d in enumerate(doms):
+        lat = esb.Lattice(D, Q, d["Nf"], d["Pr"], d["tau"], d["dims"], storage=storage)
+        lat.init_fields(*workloads.random_state(d["dims"], seed=200 + k))
+        lat.step(nsteps)
+        f, g = lat.read_populations()
+        for mode, p in res.items():
+            assert np.array_equal(f, p[k][0]), (mode, k)
+            if g is not None:
+                assert np.array_equal(g, p[k][1]), (mode, k)
