@@ -209,7 +209,7 @@ VARIANTS = ("aa", "pr", "f16", "bf16", "d3q39", "batch")
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--variants", default=",".join(VARIANTS),
                     help="comma list of variants to time beside the headline: " + ",".join(VARIANTS))
@@ -294,8 +294,8 @@ def main():
         # the same workload at the other two Prandtl numbers (same kernel,
         # other omega and nu)
         for pr in (0.5, 2.0):
-            r = time_single(esb, torch, D, Q, Nf, pr, tau, (N, N), "f32", fields, max(50, args.steps // 2),
-                            args.warmup, tune_cache)
+            r = time_single(esb, torch, D, Q, Nf, pr, tau, (N, N), "f32", fields, args.steps, args.warmup,
+                            tune_cache)
             var[f"d2q37_4096_f32_pr{pr:g}"] = {"mlups": round(r["mlups"], 1),
                                                "roofline_frac": round(bpl / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                                "streaming": "pull", "tile": r["tile"]}
