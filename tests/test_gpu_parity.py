@@ -383,3 +383,43 @@ def test_steps_captured_in_a_graph(streaming):
         lat.read_moments()     # eager work between replays
         (fa, ga), (fb, gb) = eager.read_populations(), lat.read_populations()
         assert np.array_equal(fa, fb) and np.array_equal(ga, gb), r
+
+
+def _random_cases(n=14, seed=1611):
+    """Seeded random configurations: lattice, N_f, Pr, tau, kappa, ragged
+    dims, streaming scheme and step count (admissible parameters only)."""
+    rng = np.random.default_rng(seed)
+    lats = [(2, 37), (2, 33), (3, 39)]
+    out = []
+    while len(out) < n:
+        D, Q = lats[rng.integers(len(lats))]
+        Nf = int(rng.choice([0, 1, 2, 3, 5]))
+        Pr, tau, kappa = float(rng.uniform(0.5, 2.0)), float(rng.uniform(0.55, 1.5)), float(rng.uniform(0.0, 0.9))
+        try:
+            esb.params(D, Nf, Pr, tau, kappa)
+        except esb.EsbgkError:
+            continue
+        reach = esb.lattice_info(D, Q)["reach"]
+        if D == 2:
+            dims = (int(rng.integers(reach, 70)), int(rng.integers(reach, 50)))
+            if rng.random() < 0.4:
+                dims = (64 * int(rng.integers(1, 4)), dims[1])      # rows of whole waves
+        else:
+            dims = tuple(int(rng.integers(reach, 14)) for _ in range(3))
+        out.append((D, Q, Nf, round(Pr, 3), round(tau, 3), round(kappa, 3), dims,
+                    str(rng.choice(["aa", "pull"])), int(rng.integers(1, 6))))
+    return out
+
+
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,kappa,dims,streaming,steps", _random_cases())
+def test_random_configurations_match_oracle(D, Q, Nf, Pr, tau, kappa, dims, streaming, steps):
+    fields = workloads.random_state(dims, seed=40 + steps)
+    perm, li = perm_to_oracle(D, Q)
+    lat = gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, kappa=kappa, streaming=streaming)
+    sim = oracle_run(D, Q, Nf, Pr, tau, dims, fields, steps, kappa=kappa)
+    fg, gg = lat.read_populations()
+    fo, go = sim.get_pops()
+    e = pop_error(li["w"], fg, fo[perm])
+    eg = pop_error(li["w"], gg, go[perm]) / max(1, Nf) if Nf else 0.0
+    print(f"D{D}Q{Q} Nf={Nf} Pr={Pr} tau={tau} kappa={kappa} {dims} {streaming} x {steps}: pop {e:.2e} g {eg:.2e}")
+    assert e < 3e-6 and eg < 3e-6
