@@ -423,3 +423,40 @@ def test_random_configurations_match_oracle(D, Q, Nf, Pr, tau, kappa, dims, stre
     eg = pop_error(li["w"], gg, go[perm]) / max(1, Nf) if Nf else 0.0
     print(f"D{D}Q{Q} Nf={Nf} Pr={Pr} tau={tau} kappa={kappa} {dims} {streaming} x {steps}: pop {e:.2e} g {eg:.2e}")
     assert e < 3e-6 and eg < 3e-6
+
+
+# the benchmark's other full-size workloads in the benchmark's launch
+# configuration (two-copy pull, autotuned launch shape): one step at sampled
+# cells against the oracle's collision of the GPU's own pre-step populations
+BENCH_CASES = [
+    (3, 39, 2, 0.71, 0.7, (256, 256, 256), "f32"),    # thermal Taylor-Green vortex
+    (2, 37, 3, 0.71, 0.6, (4096, 4096), "f16"),
+    (2, 37, 3, 0.71, 0.6, (4096, 4096), "bf16"),
+]
+
+
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,dims,storage", BENCH_CASES)
+def test_benchmark_workloads_sampled(D, Q, Nf, Pr, tau, dims, storage):
+    n = int(np.prod(dims))
+    fields = workloads.taylor_green_3d(dims[0]) if D == 3 else workloads.waves_noise_2d(dims[0])
+    perm, li = perm_to_oracle(D, Q)
+    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, streaming="pull")
+    lat.init_fields(*fields)
+    lat.autotune()
+    lat.step(4)
+    rng = np.random.default_rng(n % 1000)
+    cells = np.concatenate([rng.integers(0, n, 40), [0, dims[0] - 1, n - 1]])
+    nb = neighbourhood(dims, cells, li["c"])
+    f0, g0 = lat.read_cells(nb.ravel())
+    lat.step(1)
+    f1, g1 = lat.read_cells(cells)
+    inv = np.argsort(perm)
+    fo, go = oracle.collide_cells(D, Q, Nf, Pr, tau, 0.2, f0[:, inv], g0[:, inv])
+    diag = (np.arange(cells.size)[:, None], np.arange(Q)[None, :], np.arange(Q)[None, :])
+    ef = float(np.max(np.abs(f1 - fo[:, perm].reshape(cells.size, Q, Q)[diag]) / li["w"]))
+    eg = float(np.max(np.abs(g1 - go[:, perm].reshape(cells.size, Q, Q)[diag]) / li["w"])) / Nf
+    print(f"D{D}Q{Q} {dims} {storage} sampled step 4->5: f {ef:.2e} g {eg:.2e}")
+    tol = 1e-6 if storage == "f32" else 1e-4
+    assert ef < tol and eg < tol
+    del lat
+    torch.cuda.empty_cache()
