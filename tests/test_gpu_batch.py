@@ -201,3 +201,33 @@ def test_other_lattices_batch_equals_single(D, Q, doms, storage):
             assert np.array_equal(f, p[k][0]), (mode, k)
             if g is not None:
                 assert np.array_equal(g, p[k][1]), (mode, k)
+
+
+def test_benchmark_batch_equals_single_domains():
+    """The benchmark's 256-domain batch (21.8M cells), autotuned, three
+    persistent steps: the smallest and largest domains and one of each N_f
+    equal single-domain runs of the same domains bitwise."""
+    doms = workloads.batch_domains(256)
+    descs = [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms]
+    bt = esb.Batch(2, 37, descs)
+    for k, d in enumerate(doms):
+        bt.init_fields(k, *workloads.batch_fields(d))
+    bt.autotune()
+    bt.step(3, mode=esb.PERSISTENT)
+    assert bt.status() == 0
+    cells = [d["nx"] * d["ny"] for d in doms]
+    pick = {int(np.argmin(cells)), int(np.argmax(cells))}
+    for nf in (0, 1, 3):
+        pick.add(next(k for k, d in enumerate(doms) if d["Nf"] == nf))
+    for k in sorted(pick):
+        d = doms[k]
+        lat = esb.Lattice(2, 37, d["Nf"], d["Pr"], d["tau"], (d["nx"], d["ny"]))
+        lat.init_fields(*workloads.batch_fields(d))
+        lat.step(3)
+        f, g = lat.read_populations()
+        fb, gb = bt.read_populations(k)
+        assert np.array_equal(f, fb), k
+        if g is not None:
+            assert np.array_equal(g, gb), k
+    del bt
+    torch.cuda.empty_cache()
