@@ -203,7 +203,7 @@ def cpu_baseline(seconds=12.0):
             "single_thread_value": round(v1, 3)}
 
 
-VARIANTS = ("aa", "pr", "f16", "bf16", "d3q39", "batch")
+VARIANTS = ("aa", "pr", "f16", "bf16", "d3q39", "d2q33", "batch")
 
 
 def main():
@@ -324,7 +324,27 @@ def main():
                                     "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                     "GBs_per_step": round(b / (r["total_ms"] / s3 * 1e-3) / 1e9, 1),
                                     "streaming": "pull", "tile": r["tile"]}
+        del r
+        torch.cuda.empty_cache()
+        # the same vortex with BF16 deviation storage (f and g paired)
+        r = time_single(esb, torch, 3, 39, 2, 0.71, 0.7, (n3, n3, n3), "bf16", f3, s3, args.warmup, tune_cache)
+        b = bytes_per_cell(39, 2, "bf16") * n3 ** 3
+        var["d3q39_256cube_bf16"] = {"mlups": round(r["mlups"], 1),
+                                     "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                     "streaming": "pull", "tile": r["tile"]}
         del r, f3
+        torch.cuda.empty_cache()
+    if "d2q33" in variants:
+        # the shock-tube lattice (|c| up to 4) on the 4096^2 wave workload, FP32
+        n2 = 4096
+        f2 = workloads.waves_noise_2d(n2)
+        r = time_single(esb, torch, 2, 33, 3, 0.71, 0.6, (n2, n2), "f32", f2, max(50, args.steps // 2), args.warmup,
+                        tune_cache)
+        b = bytes_per_cell(33, 2, "f32") * n2 * n2
+        var["d2q33_4096_f32"] = {"mlups": round(r["mlups"], 1),
+                                 "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "streaming": "pull", "tile": r["tile"]}
+        del r, f2
         torch.cuda.empty_cache()
     if "batch" in variants:
         var["batched_256_d2q37_f32"] = time_batch(esb, torch, workloads, args.batch_steps, tune_cache)
