@@ -230,7 +230,8 @@ int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch
  * size (a multiple of 64 in [64, 512]; 0 = 256); order = work-group order
  * over the cells (0 = default = 1; 1 = dispatch order; 2 = contiguous runs
  * of cells per XCD); policy = cache policy of the population loads and
- * stores (0 = default = 1; 1 = normal; 2 = non-temporal); cells_per_item =
+ * stores (0 = default = 1; 1 = normal; 2 = non-temporal loads and stores;
+ * 3 = non-temporal stores, normal loads); cells_per_item =
  * consecutive chunks of `block` cells one work-group sweeps (1..64; 0 = 1).
  * ESBGK_EINVAL otherwise.  Results do not depend on the launch shape. */
 int esbgk_set_tile(esbgk_t *h, int parity, int block, int order, int policy, int cells_per_item);
@@ -301,7 +302,7 @@ int esbgk_batch_step(esbgk_batch_t *b, int64_t n, int mode);
 int esbgk_batch_set_tile(esbgk_batch_t *b, int block, int policy, int window, double group_bytes);
 
 /* The batch's autotuner: time the persistent mode (a few steps) for each
- * work-group size in {128, 256, 512} and both cache policies, on the
+ * work-group size in {128, 256, 512} and cache policy 0, 2 and 3, on the
  * batch's own state, put that state (and the step count) back bitwise,
  * and keep the fastest shape; window and domain grouping stay as set.
  * With cache_path the choice is looked up first (keyed by lattice,
@@ -310,7 +311,7 @@ int esbgk_batch_set_tile(esbgk_batch_t *b, int block, int policy, int window, do
  * copy of the batch storage on the device while it runs.  Synchronous. */
 int esbgk_batch_autotune(esbgk_batch_t *b, double budget_ms, const char *cache_path);
 
-/* Current work-group size and cache policy (0 or 2) of the batched kernels. */
+/* Current work-group size and cache policy (0, 2 or 3) of the batched kernels. */
 int esbgk_batch_get_tile(const esbgk_batch_t *b, int *block, int *policy);
 
 /* esbgk_batch_step bracketed by HIP events on the batch's stream; *ms is

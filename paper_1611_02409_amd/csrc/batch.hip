@@ -331,12 +331,12 @@ int esbgk_batch_set_tile(esbgk_batch_t *b, int block, int policy, int window, do
     clear_error();
     if (int rc = bcheck(b)) return rc;
     if (block == 0) block = 256;
-    if (block < 64 || block > 512 || (block & 63) || policy < 0 || policy > 2 || window < 0 || window > 4096) {
-        set_error("block must be a multiple of 64 in [64, 512], policy 0..2, window 0..4096");
+    if (block < 64 || block > 512 || (block & 63) || policy < 0 || policy > 3 || window < 0 || window > 4096) {
+        set_error("block must be a multiple of 64 in [64, 512], policy 0..3, window 0..4096");
         return ESBGK_EINVAL;
     }
     b->block = block;
-    b->policy = policy == 2 ? 1 : 0;
+    b->policy = policy == 2 ? 1 : policy == 3 ? 2 : 0;
     b->window = window == 0 ? 1 : (uint32_t)window;
     if (group_bytes > 0) b->group_bytes = group_bytes;
     b->tables_block = -1;   // group layout may have changed
@@ -591,12 +591,12 @@ int esbgk_batch_autotune(esbgk_batch_t *b, double budget_ms, const char *cache_p
     const int64_t steps0 = b->steps;
     int rc = ESBGK_OK;
     if (hipMemcpyAsync(save, b->buf, b->bytes, hipMemcpyDeviceToDevice, b->stream) != hipSuccess) rc = ESBGK_EDEVICE;
-    const int old_block = b->block, old_policy = b->policy == 1 ? 2 : 0;
+    const int old_block = b->block, old_policy = b->policy == 1 ? 2 : b->policy == 2 ? 3 : 0;
     int best_block = old_block, best_policy = old_policy;
     double best = 1e30;
     const auto t0 = std::chrono::steady_clock::now();
     for (int blk : {256, 512, 128})
-        for (int pol : {0, 2}) {
+        for (int pol : {0, 2, 3}) {
             const double el = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             if (rc || (budget_ms > 0 && el > budget_ms && best < 1e30)) continue;
             if ((rc = esbgk_batch_set_tile(b, blk, pol, window, gbytes))) break;
@@ -637,7 +637,7 @@ int esbgk_batch_get_tile(const esbgk_batch_t *b, int *block, int *policy) {
     clear_error();
     if (int rc = bcheck(b)) return rc;
     if (block) *block = b->block;
-    if (policy) *policy = b->policy == 1 ? 2 : 0;
+    if (policy) *policy = b->policy == 1 ? 2 : b->policy == 2 ? 3 : 0;
     return ESBGK_OK;
 }
 

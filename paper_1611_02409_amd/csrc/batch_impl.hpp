@@ -76,9 +76,9 @@ __device__ __forceinline__ void tile_step(char *base, const DomDev &dd, uint32_t
     else nb.own = cell * kElemBytes<S, HAS_G>;
     const Sets R(base + dd.f_off, HAS_G ? base + dd.g_off : nullptr, dd.pb, dd.sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
-    gather<L, S, ODD, HAS_G, CP>(R, nb, F, E);
+    gather<L, S, ODD, HAS_G, load_aux(CP)>(R, nb, F, E);
     collide<L, HAS_G, TargetReal<S>>(dd.coll, F, E);
-    scatter<L, S, ODD, HAS_G, CP>(R, nb, F, E);
+    scatter<L, S, ODD, HAS_G, store_aux(CP)>(R, nb, F, E);
 }
 
 template <class L, int S, int CP>
@@ -193,7 +193,8 @@ template <class L, int S>
 struct BatchOpsImpl {
     static void step(char *base, const DomDev *doms, const uint32_t *tile_dom, const uint32_t *tile_cell,
                      uint32_t tiles, int block, bool odd, int policy, hipStream_t s) {
-        if (policy) k_batch_step<L, S, 2><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
+        if (policy == 1) k_batch_step<L, S, 2><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
+        else if (policy == 2) k_batch_step<L, S, 3><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
         else k_batch_step<L, S, 0><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
     }
     template <int CP>
@@ -202,12 +203,14 @@ struct BatchOpsImpl {
         else return &k_batch_persistent<L, S, CP>;
     }
     static void persistent(char *base, const BatchDev &b, uint32_t grid, int block, int policy, hipStream_t s) {
-        if (policy) kernel<2>()<<<grid, block, 0, s>>>(base, b);
+        if (policy == 1) kernel<2>()<<<grid, block, 0, s>>>(base, b);
+        else if (policy == 2) kernel<3>()<<<grid, block, 0, s>>>(base, b);
         else kernel<0>()<<<grid, block, 0, s>>>(base, b);
     }
     static int occupancy(int block, int policy, int *blocks_per_cu) {
-        hipError_t e = policy ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<2>(), block, 0)
-                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<0>(), block, 0);
+        hipError_t e = policy == 1   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<2>(), block, 0)
+                       : policy == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<3>(), block, 0)
+                                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<0>(), block, 0);
         return e == hipSuccess ? 0 : -1;
     }
     static constexpr BatchOps ops{&step, &persistent, &occupancy};

@@ -916,15 +916,15 @@ int esbgk_set_tile(esbgk_t *h, int parity, int block, int order, int policy, int
         set_error("block must be a multiple of 64 in [64, 512] (got %d)", block);
         return ESBGK_EINVAL;
     }
-    if (parity < -1 || parity > 1 || order < 0 || order > 2 || policy < 0 || policy > 2 || cells_per_item < 1 ||
+    if (parity < -1 || parity > 1 || order < 0 || order > 2 || policy < 0 || policy > 3 || cells_per_item < 1 ||
         cells_per_item > 64) {
-        set_error("need parity -1..1, order and policy 0..2, cells_per_item 1..64");
+        set_error("need parity -1..1, order 0..2, policy 0..3, cells_per_item 1..64");
         return ESBGK_EINVAL;
     }
     Tile t;
     t.block = block;
     t.remap = order == 2 ? 1 : 0;
-    t.policy = policy == 2 ? 1 : 0;
+    t.policy = policy == 2 ? 1 : policy == 3 ? 2 : 0;
     t.cpi = cells_per_item;
     if (parity != 1) h->tile[0] = t;
     if (parity != 0) h->tile[1] = t;
@@ -941,7 +941,7 @@ int esbgk_get_tile(const esbgk_t *h, int parity, int *block, int *order, int *po
     const Tile &t = h->tile[parity];
     if (block) *block = t.block;
     if (order) *order = t.remap ? 2 : 1;
-    if (policy) *policy = t.policy ? 2 : 1;
+    if (policy) *policy = t.policy + 1;
     if (cells_per_item) *cells_per_item = t.cpi;
     return ESBGK_OK;
 }
@@ -987,7 +987,7 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
     int rc = ESBGK_OK;
     for (int block : {256, 512, 128})
         for (int remap : {0, 1})
-            for (int policy : {0, 1})
+            for (int policy : {0, 1, 2})
                 for (int cpi : {1, 4, 16}) {
                     const double el =
                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
@@ -1038,7 +1038,7 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
         }
         for (int par = 0; par < 2; par++)
             std::fprintf(fp, "%s parity %d block %d order %d policy %d cpi %d ms %.4f\n", key.c_str(), par,
-                         bestt[par].block, bestt[par].remap ? 2 : 1, bestt[par].policy ? 2 : 1, bestt[par].cpi,
+                         bestt[par].block, bestt[par].remap ? 2 : 1, bestt[par].policy + 1, bestt[par].cpi,
                          best[par]);
         std::fclose(fp);
     }

@@ -843,6 +843,13 @@ struct WallSet {
     int reach;
 };
 
+// Cache policy code of the step kernels: 0 default; 2 non-temporal loads and
+// stores; 3 non-temporal stores with default loads (the reads at x - c_i
+// then keep their lines in L2 for the neighbouring work-groups, while the
+// stores, read again only in the next step, do not displace them).
+constexpr int load_aux(int policy) { return policy == 2 ? 2 : 0; }
+constexpr int store_aux(int policy) { return policy == 2 || policy == 3 ? 2 : 0; }
+
 // XCD-aware block order: the eight XCDs take blocks round-robin; give XCD k a
 // contiguous run of logical blocks so that neighbouring tiles share its L2.
 __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {

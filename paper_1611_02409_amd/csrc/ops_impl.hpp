@@ -28,22 +28,22 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(ROW && S !=
         if constexpr (ROW) {
             RowNbr<L, kElemBytes<S, HAS_G>> nb;
             nb.init(cell, g);
-            if (nb.inner) gather<L, S, LAY, HAS_G, CP>(R, nb.v, F, E);
-            else gather<L, S, LAY, HAS_G, CP>(R, nb.edge(), F, E);
+            if (nb.inner) gather<L, S, LAY, HAS_G, load_aux(CP)>(R, nb.v, F, E);
+            else gather<L, S, LAY, HAS_G, load_aux(CP)>(R, nb.edge(), F, E);
             collide<L, HAS_G, TargetReal<S>>(cp, F, E);
             if constexpr (LAY == LAY_PULL) {
-                scatter<L, S, LAY, HAS_G, CP>(W, nb.v, F, E);   // own cell only
+                scatter<L, S, LAY, HAS_G, store_aux(CP)>(W, nb.v, F, E);   // own cell only
             } else {
-                if (nb.inner) scatter<L, S, LAY, HAS_G, CP>(W, nb.v, F, E);
-                else scatter<L, S, LAY, HAS_G, CP>(W, nb.edge(), F, E);
+                if (nb.inner) scatter<L, S, LAY, HAS_G, store_aux(CP)>(W, nb.v, F, E);
+                else scatter<L, S, LAY, HAS_G, store_aux(CP)>(W, nb.edge(), F, E);
             }
         } else {
             Nbr<L, kElemBytes<S, HAS_G>> nb;
             if constexpr (LAY != LAY_EVEN) nb.init(cell, g);
             else nb.own = cell * kElemBytes<S, HAS_G>;
-            gather<L, S, LAY, HAS_G, CP>(R, nb, F, E);
+            gather<L, S, LAY, HAS_G, load_aux(CP)>(R, nb, F, E);
             collide<L, HAS_G, TargetReal<S>>(cp, F, E);
-            scatter<L, S, LAY, HAS_G, CP>(W, nb, F, E);
+            scatter<L, S, LAY, HAS_G, store_aux(CP)>(W, nb, F, E);
         }
     }
 }
@@ -367,10 +367,12 @@ struct OpsImpl {
             }
         });
     }
-    // policy 0: default caching; 1: non-temporal loads and stores
+    // Tile::policy 0: default caching; 1: non-temporal loads and stores;
+    // 2: non-temporal stores only (kernel policy codes 0, 2, 3)
     static void step(char *fb, char *gb, char *wfb, char *wgb, uint32_t pb, uint32_t sb, const Geom &g,
                      const Coll &c, int lay, bool has_g, const Tile &t, hipStream_t s) {
-        if (t.policy) step_cp<2>(fb, gb, wfb, wgb, pb, sb, g, c, lay, has_g, t.block, t.remap, t.cpi, s);
+        if (t.policy == 1) step_cp<2>(fb, gb, wfb, wgb, pb, sb, g, c, lay, has_g, t.block, t.remap, t.cpi, s);
+        else if (t.policy == 2) step_cp<3>(fb, gb, wfb, wgb, pb, sb, g, c, lay, has_g, t.block, t.remap, t.cpi, s);
         else step_cp<0>(fb, gb, wfb, wgb, pb, sb, g, c, lay, has_g, t.block, t.remap, t.cpi, s);
     }
     static void init(char *fb, char *gb, uint32_t pb, uint32_t sb, const Geom &g, const Coll &c, const float *fields,

@@ -62,7 +62,7 @@ int fields_to_dev(const double *rho, const double *u, const double *T, int D, ui
 struct Tile {
     int block = 256;   // work-group size
     int remap = 0;     // 1: contiguous cell runs per XCD
-    int policy = 0;    // 1: non-temporal population loads and stores
+    int policy = 0;    // 0 default caching; 1 non-temporal population loads and stores; 2 non-temporal stores only
     int cpi = 1;       // chunks of `block` cells per work-group
 };
 

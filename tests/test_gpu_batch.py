@@ -98,13 +98,15 @@ def test_batch_matches_oracle():
         assert abs(t[0] - sim.totals()[0]) / np.prod(d["dims"]) < 1e-7
 
 
-@pytest.mark.parametrize("block,window,group_bytes", [(64, 3, 2e6), (512, 1, 0.0), (128, 16, 1e5)])
-def test_persistent_windows_and_groups(block, window, group_bytes):
+@pytest.mark.parametrize("block,window,group_bytes,policy", [(64, 3, 2e6, 0), (512, 1, 0.0, 2), (128, 16, 1e5, 3),
+                                                              (256, 1, 0.0, 3)])
+def test_persistent_windows_and_groups(block, window, group_bytes, policy):
     """Domain groups advanced several steps at a time (and tiny groups,
-    one domain each) give the same result as step-by-step execution."""
+    one domain each), under each cache policy, give the same result as
+    step-by-step execution."""
     ref = make_batch()
     ref.step(9, mode=esb.PER_DOMAIN)
-    b = make_batch(block=block, window=window, group_bytes=group_bytes)
+    b = make_batch(block=block, window=window, group_bytes=group_bytes, policy=policy)
     b.step(9, mode=esb.PERSISTENT)
     assert b.status() == 0
     assert same(pops(b), pops(ref))
@@ -155,7 +157,7 @@ def test_autotune_restores_state_and_caches(tmp_path, storage):
     b.step(3)
     before = pops(a)
     blk, pol = a.autotune(cache_path=cache)
-    assert blk in (128, 256, 512) and pol in (0, 2)
+    assert blk in (128, 256, 512) and pol in (0, 2, 3)
     assert same(before, pops(a))
     a.step(5)
     b.step(5)

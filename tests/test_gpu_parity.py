@@ -269,6 +269,8 @@ def test_write_populations_roundtrip(streaming):
     [(-1, 512, 2, 2, 16)],
     [(0, 256, 1, 2, 4), (1, 128, 2, 1, 3)],
     [(0, 512, 2, 1, 64), (1, 256, 1, 2, 1)],
+    [(-1, 512, 1, 3, 1)],
+    [(0, 256, 2, 3, 4), (1, 512, 1, 3, 2)],
 ])
 @pytest.mark.parametrize("dims", [(77, 53), (256, 7)])
 def test_launch_shape_does_not_change_results(tiles, dims):
