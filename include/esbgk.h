@@ -251,8 +251,9 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
  * `cells` cells read and written once per launch with no arithmetic (1 <=
  * reps timed launches on the default stream, 256 <= cells <= 2.8e7).
  * *gbps counts read plus written bytes and is the best of three placements
- * (in place on each of two buffers, and a copy from one to the other) and
- * four occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU).
+ * (in place on each of two buffers, and a copy from one to the other), four
+ * occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU) and two store
+ * cache policies (default and non-temporal).
  * Allocates and frees its own buffers (four sets of 37 planes).  A roofline
  * reference next to the published HBM peak, not part of the scheme. */
 int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps);

@@ -12,7 +12,8 @@ namespace {
 // in place, as A-A does; another buffer: as two-copy pull does).
 // `lds` bytes of dynamic LDS per work-group only limit how many work-groups
 // share a CU (the pattern streams best at a few waves per SIMD); touch is 0.
-template <int NP>
+// SCP: cache-policy bits of the stores (0 default, 2 non-temporal).
+template <int NP, int SCP>
 __global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_t ncell, uint32_t set_bytes, int touch) {
     extern __shared__ float occupancy_lds[];
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,7 +28,7 @@ __global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_
     for (int i = 0; i < NP; i++) s += v[i];
     if (touch) occupancy_lds[threadIdx.x] = s;
 #pragma unroll
-    for (int i = 0; i < NP; i++) st<ST_F32>(v[i] + s * 1e-30f, i < NP / 2 ? W.f : W.g, c * 4u, W.so(i % (NP / 2)));
+    for (int i = 0; i < NP; i++) st<ST_F32, SCP>(v[i] + s * 1e-30f, i < NP / 2 ? W.f : W.g, c * 4u, W.so(i % (NP / 2)));
 }
 
 }  // namespace
@@ -37,8 +38,9 @@ using namespace esbgk;
 
 // Best of three placements of the pattern (in place on each of two buffers
 // allocated one after the other, and a copy from one to the other: where a
-// buffer lands in HBM moves such streams by a few per cent) and of four
-// occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU).
+// buffer lands in HBM moves such streams by a few per cent), of four
+// occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU) and of two
+// store policies (default and non-temporal, the two the step kernels use).
 extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     clear_error();
     if (cells < 256 || cells > (int64_t)14000000 * 2 || reps < 1 || !gbps) {
@@ -67,10 +69,11 @@ extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     const size_t lds_for[4] = {96 * 1024, 60 * 1024, 44 * 1024, 0};
     for (int pass = 0; pass < 3 && rc == ESBGK_OK; pass++) {
         char *src = p[pass == 1 ? 1 : 0], *dst = p[pass == 0 ? 0 : 1];
-        for (size_t lds : lds_for) {
-            for (int w = 0; w < 2; w++) k_stream_rw<74><<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
+        for (int pol = 0; pol < 2 && rc == ESBGK_OK; pol++) for (size_t lds : lds_for) {
+            auto kern = pol ? k_stream_rw<74, 2> : k_stream_rw<74, 0>;
+            for (int w = 0; w < 2; w++) kern<<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
             (void)hipEventRecord(e0, nullptr);
-            for (int r = 0; r < reps; r++) k_stream_rw<74><<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
+            for (int r = 0; r < reps; r++) kern<<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
             (void)hipEventRecord(e1, nullptr);
             if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                 set_error("stream kernel failed");
