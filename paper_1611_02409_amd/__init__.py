@@ -41,6 +41,8 @@ def _storage_code(storage: str, streaming: str = "aa") -> int:
     if streaming not in STREAMING:
         raise ValueError(f"streaming must be one of {sorted(STREAMING)}")
     return STORAGE[storage] | STREAMING[streaming]
+
+
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EDEVICE", -5: "ESTATE", -6: "ENONFINITE", -7: "EIO"}
 
 

@@ -307,7 +307,8 @@ int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const do
     }
     const DomainSetup &s = b->su[k];
     const uint64_t n = s.geom.ncell;
-    std::vector<float> host((2 + b->D) * n);
+    std::vector<float> host;
+    if (int rc = host_buffer(host, (2 + b->D) * n)) return rc;
     if (int rc = fields_to_dev(rho, u, T, b->D, n, host.data())) return rc;
     void *tmp = nullptr;
     ESBGK_HIP(hipMalloc(&tmp, host.size() * sizeof(float)));
@@ -402,9 +403,12 @@ int esbgk_batch_step_timed(esbgk_batch_t *b, int64_t n, int mode, double *ms) {
         set_error("ms is NULL");
         return ESBGK_EINVAL;
     }
-    hipEvent_t e0, e1;
-    ESBGK_HIP(hipEventCreate(&e0));
-    ESBGK_HIP(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        set_error("event creation failed");
+        return ESBGK_EDEVICE;
+    }
     (void)hipEventRecord(e0, b->stream);
     int rc = esbgk_batch_step(b, n, mode);
     (void)hipEventRecord(e1, b->stream);
@@ -467,7 +471,8 @@ int esbgk_batch_read_moments(esbgk_batch_t *b, int k, double *rho, double *u, do
     ESBGK_HIP(hipMalloc(&tmp, planes * n * sizeof(float)));
     b->ops->moments(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * b->Q), s.geom, s.coll,
                     (b->steps & 1) ? LAY_ODD : LAY_EVEN, s.npop == 2, tmp, P != nullptr, b->stream);
-    std::vector<float> host(planes * n);
+    std::vector<float> host;
+    if (int rc = host_buffer(host, planes * n)) return rc;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = hipMemcpyAsync(host.data(), tmp, host.size() * sizeof(float), hipMemcpyDeviceToHost, b->stream);
@@ -536,7 +541,8 @@ int esbgk_batch_read_populations(esbgk_batch_t *b, int k, double *f, double *g) 
     ESBGK_HIP(hipMalloc(&tmp, n * Q * npop * sizeof(float)));
     b->ops->cells(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * Q), s.geom, s.coll,
                   (b->steps & 1) ? LAY_ODD : LAY_EVEN, npop == 2, nullptr, (uint32_t)n, tmp, b->stream);
-    std::vector<float> host(n * Q * npop);
+    std::vector<float> host;
+    if (int rc = host_buffer(host, n * Q * npop)) return rc;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = hipMemcpyAsync(host.data(), tmp, host.size() * sizeof(float), hipMemcpyDeviceToHost, b->stream);

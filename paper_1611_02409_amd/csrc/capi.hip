@@ -383,6 +383,20 @@ int launch_error() {
     return ESBGK_OK;
 }
 
+// HIP events owned by the call (destroyed on every return path).
+struct Events {
+    std::vector<hipEvent_t> e;
+    ~Events() {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    int create(uint64_t n) {
+        if (int rc = host_buffer(e, n)) return rc;
+        for (auto &x : e) ESBGK_HIP(hipEventCreate(&x));
+        return ESBGK_OK;
+    }
+};
+
 // Device scratch of at least n bytes owned by the call.
 struct DevTmp {
     void *p = nullptr;
@@ -478,12 +492,7 @@ int esbgk_init_fields(esbgk_t *h, const double *rho, const double *u, const doub
     if (int rc = check(h)) return rc;
     const uint64_t n = h->su.geom.ncell;
     std::vector<float> host;
-    try {
-        host.resize((2 + h->D) * n);
-    } catch (...) {
-        set_error("host allocation failed");
-        return ESBGK_ENOMEM;
-    }
+    if (int rc = host_buffer(host, (2 + h->D) * n)) return rc;
     if (int rc = fields_to_dev(rho, u, T, h->D, n, host.data())) return rc;
     DevTmp tmp;
     ESBGK_HIP(hipMalloc(&tmp.p, host.size() * sizeof(float)));
@@ -624,7 +633,8 @@ int esbgk_read_moments(esbgk_t *h, double *rho, double *u, double *T, double *P)
     h->ops->moments(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->lay(), h->has_g(),
                     (float *)tmp.p, P != nullptr, h->stream);
     if (int rc = launch_error()) return rc;
-    std::vector<float> host(planes * n);
+    std::vector<float> host;
+    if (int rc = host_buffer(host, planes * n)) return rc;
     ESBGK_HIP(hipMemcpyAsync(host.data(), tmp.p, host.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     for (uint64_t k = 0; k < n; k++) {
@@ -675,7 +685,8 @@ int esbgk_read_cells(esbgk_t *h, int64_t n, const int64_t *cells, double *f, dou
         set_error("too many cells requested");
         return ESBGK_EINVAL;
     }
-    std::vector<uint32_t> list(n);
+    std::vector<uint32_t> list;
+    if (int rc = host_buffer(list, n)) return rc;
     for (int64_t k = 0; k < n; k++) {
         if (cells[k] < 0 || cells[k] >= (int64_t)h->su.geom.ncell) {
             set_error("cell index %lld out of range", (long long)cells[k]);
@@ -691,7 +702,8 @@ int esbgk_read_cells(esbgk_t *h, int64_t n, const int64_t *cells, double *f, dou
     h->ops->cells(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->lay(), h->has_g(),
                   (const uint32_t *)dl.p, (uint32_t)n, (float *)dout.p, h->stream);
     if (int rc = launch_error()) return rc;
-    std::vector<float> host((size_t)n * Q * npop);
+    std::vector<float> host;
+    if (int rc = host_buffer(host, (size_t)n * Q * npop)) return rc;
     ESBGK_HIP(hipMemcpyAsync(host.data(), dout.p, host.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     const LatticeConsts &lc = h->su.lc;
@@ -718,7 +730,8 @@ int esbgk_read_populations(esbgk_t *h, double *f, double *g) {
     h->ops->cells(h->fb(), h->gb(), h->pb(), h->sb(), h->su.geom, h->su.coll, h->lay(), h->has_g(), nullptr,
                   (uint32_t)n, (float *)dout.p, h->stream);
     if (int rc = launch_error()) return rc;
-    std::vector<float> host(n * Q * npop);
+    std::vector<float> host;
+    if (int rc = host_buffer(host, n * Q * npop)) return rc;
     ESBGK_HIP(hipMemcpyAsync(host.data(), dout.p, host.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     const LatticeConsts &lc = h->su.lc;
@@ -742,7 +755,8 @@ int esbgk_write_populations(esbgk_t *h, const double *f, const double *g) {
     const uint64_t n = h->su.geom.ncell;
     const int Q = h->Q, npop = h->su.npop;
     const LatticeConsts &lc = h->su.lc;
-    std::vector<float> host(n * Q * npop);
+    std::vector<float> host;
+    if (int rc = host_buffer(host, n * Q * npop)) return rc;
     for (int i = 0; i < Q; i++) {
         const int sh = lc.shell_of[i];
         const double w = lc.wshell[sh];
@@ -788,12 +802,7 @@ int esbgk_save(esbgk_t *h, const char *path) {
         return ESBGK_EINVAL;
     }
     std::vector<char> host;
-    try {
-        host.resize(h->su.copy_bytes);
-    } catch (...) {
-        set_error("host allocation failed");
-        return ESBGK_ENOMEM;
-    }
+    if (int rc = host_buffer(host, h->su.copy_bytes)) return rc;
     // the current state only (one copy)
     ESBGK_HIP(hipMemcpyAsync(host.data(), h->fb(), h->su.copy_bytes, hipMemcpyDeviceToHost, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
@@ -851,7 +860,16 @@ int esbgk_load(esbgk_t *h, const char *path) {
         set_error("checkpoint %s does not match this lattice (shape, N_f or storage)", path);
         return ESBGK_EINVAL;
     }
-    std::vector<char> host(hd.bytes);
+    if (hd.version != 2 || hd.steps < 0) {
+        std::fclose(fp);
+        set_error("%s has an unknown version or a negative step count", path);
+        return ESBGK_EIO;
+    }
+    std::vector<char> host;
+    if (int rc = host_buffer(host, hd.bytes)) {
+        std::fclose(fp);
+        return rc;
+    }
     const bool ok = std::fread(host.data(), 1, host.size(), fp) == host.size();
     std::fclose(fp);
     if (!ok) {
@@ -885,8 +903,9 @@ int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch
         set_error("need n >= 1 and total_ms");
         return ESBGK_EINVAL;
     }
-    std::vector<hipEvent_t> ev(n + 1);
-    for (auto &e : ev) ESBGK_HIP(hipEventCreate(&e));
+    Events events;
+    if (int rc = events.create((uint64_t)n + 1)) return rc;
+    std::vector<hipEvent_t> &ev = events.e;
     int rc = ESBGK_OK;
     ESBGK_HIP(hipEventRecord(ev[0], h->stream));
     for (int64_t k = 0; k < n; k++) {
@@ -903,7 +922,6 @@ int esbgk_step_timed(esbgk_t *h, int64_t n, double *total_ms, double *per_launch
             ESBGK_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
             per_launch_ms[k] = ms;
         }
-    for (auto &e : ev) (void)hipEventDestroy(e);
     return rc;
 }
 
@@ -979,8 +997,9 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
     ESBGK_HIP(hipMemcpyAsync(save.p, h->buf, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
     const int64_t steps0 = h->steps;
     const bool from_step0 = h->from_step;
-    hipEvent_t ev[7];
-    for (auto &e : ev) ESBGK_HIP(hipEventCreate(&e));
+    Events events;
+    if (int rc = events.create(7)) return rc;
+    const std::vector<hipEvent_t> &ev = events.e;
     double best[2] = {1e30, 1e30};
     Tile bestt[2] = {h->tile[0], h->tile[1]};
     const auto t_start = std::chrono::steady_clock::now();
@@ -1022,7 +1041,6 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
                         }
                     }
                 }
-    for (auto &e : ev) (void)hipEventDestroy(e);
     ESBGK_HIP(hipMemcpyAsync(h->buf, save.p, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->steps = steps0;

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "../../include/esbgk.h"
 #include "kernels.hpp"
@@ -26,6 +27,20 @@ void clear_error();
             return e_ == hipErrorOutOfMemory ? ESBGK_ENOMEM : ESBGK_EDEVICE;                             \
         }                                                                                                \
     } while (0)
+
+// Sizes a host buffer for a C ABI call; a failed allocation becomes
+// ESBGK_ENOMEM with the message set instead of an exception that would
+// cross the C boundary.
+template <class T>
+int host_buffer(std::vector<T> &v, uint64_t n) {
+    try {
+        v.resize(n);
+    } catch (...) {
+        set_error("host allocation of %llu bytes failed", (unsigned long long)(n * sizeof(T)));
+        return ESBGK_ENOMEM;
+    }
+    return ESBGK_OK;
+}
 
 FastDiv make_fastdiv(uint32_t d);
 
