@@ -29,7 +29,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS and % of HBM peak, FP32 vs FP16-storage vs batched, at stated error vs FP64"
 HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "k_step_d2q37_f32_4096_traffic.json")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def traffic_path(lattice):
+    """Committed HBM-traffic summary of the FP32 step kernels of one
+    benchmark workload (D2Q37 4096^2 or D3Q39 256^3, 2^24 cells each)."""
+    size = "4096" if lattice == "D2Q37" else "256cube"
+    return os.path.join(PROFILE_DIR, f"k_step_{lattice.lower()}_f32_{size}_traffic.json")
 
 
 def kernel_source_hash() -> str:
@@ -83,18 +90,39 @@ def roofline(bytes_per_launch, launch_ms, peak=HBM_PEAK_GBS, traffic=None):
             "traffic": traffic}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of one FP32 D2Q37 4096^2 step kernel ("pull",
-    "aa_even" or "aa_odd") from the committed rocprofv3 counter summary, if it
-    was taken from the current kernel source; otherwise None."""
+# kernel cache-policy template argument of each ABI cache policy (1 default,
+# 2 non-temporal loads and stores, 3 non-temporal stores)
+CP_OF_POLICY = {1: 0, 2: 2, 3: 3}
+LAYOUT_NAMES = {0: "aa_even", 1: "aa_odd", 2: "pull"}
+
+
+def traffic_key(layout, cp, block, cpi):
+    return f"{layout} cp{cp} wg{block} cpi{cpi}"
+
+
+def measured_traffic(layout, tile, lattice="D2Q37"):
+    """HBM bytes per launch of one FP32 step kernel (layout "pull",
+    "aa_even" or "aa_odd"; tile = (block, order, policy, cells_per_item) as
+    the autotuner reports it) from the committed rocprofv3 counter summary,
+    if that summary holds this launch shape and was taken from the current
+    kernel source; otherwise None."""
     try:
-        with open(PROFILE_TRAFFIC) as fh:
+        with open(traffic_path(lattice)) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("kernels", {}).get(kernel, {}).get("hbm_bytes_per_launch")
+    block, _, policy, cpi = tile
+    key = traffic_key(layout, CP_OF_POLICY.get(policy, -1), block, cpi)
+    return d.get("kernels", {}).get(key, {}).get("hbm_bytes_per_launch")
+
+
+def pull_traffic(tiles, lattice="D2Q37"):
+    """Mean HBM bytes per launch of the pull kernel over the even- and
+    odd-step launch shapes (None unless both were measured)."""
+    t = [measured_traffic("pull", tuple(x), lattice) for x in tiles]
+    return None if None in t else round(float(np.mean(t)))
 
 
 def _counter_rows(d):
@@ -106,10 +134,11 @@ def _counter_rows(d):
     rows = []
     for path in glob.glob(os.path.join(d, "**", "*.db"), recursive=True):
         db = sqlite3.connect(path)
-        for name, counter, value, disp, grid in db.execute(
-                "select kernel_name, counter_name, value, dispatch_id, grid_size from counters_collection"):
+        for name, counter, value, disp, grid, wg in db.execute(
+                "select kernel_name, counter_name, value, dispatch_id, grid_size, workgroup_size "
+                "from counters_collection"):
             rows.append({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value,
-                         "Dispatch_Id": f"{path}:{disp}", "Grid_Size": grid})
+                         "Dispatch_Id": f"{path}:{disp}", "Grid_Size": grid, "Workgroup_Size": wg})
         db.close()
     for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
         with open(path) as fh:
@@ -117,59 +146,67 @@ def _counter_rows(d):
     return rows
 
 
-def _per_dispatch(rows, counter, match, grid=None):
+def _per_dispatch(rows, counter, match):
     """Sum of `counter` (KiB) per dispatch of kernels whose name contains all
-    of `match` (and, if given, whose grid has `grid` work-items)."""
+    of `match`, grouped by (kernel name, grid size, work-group size)."""
     out = {}
     for r in rows:
         if r.get("Counter_Name") != counter or not all(m in r.get("Kernel_Name", "") for m in match):
             continue
-        if grid is not None and int(r.get("Grid_Size", grid)) != grid:
-            continue
+        g = (r["Kernel_Name"], int(r.get("Grid_Size", 0)), int(r.get("Workgroup_Size", 0)))
         k = r.get("Dispatch_Id") or r.get("Correlation_Id")
-        out[k] = out.get(k, 0.0) + float(r["Counter_Value"])
-    return list(out.values())
+        out.setdefault(g, {})
+        out[g][k] = out[g].get(k, 0.0) + float(r["Counter_Value"])
+    return {g: list(v.values()) for g, v in out.items()}
 
 
-# demangled-name prefixes of the FP32 (storage 0) D2Q37 step kernels with
-# both populations, by layout (0 A-A even, 1 A-A odd, 2 pull)
-STEP_KERNELS = {"pull": "k_step<esbgk::LatD2Q37, 0, 2, true,", "aa_even": "k_step<esbgk::LatD2Q37, 0, 0, true,",
-                "aa_odd": "k_step<esbgk::LatD2Q37, 0, 1, true,"}
-
-
-def ingest_counters(fetch_dir, write_dir, ncell=4096 * 4096):
+def ingest_counters(fetch_dir, write_dir, lattice="D2Q37", ncell=4096 * 4096):
     """Turn two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
-    WRITE_SIZE, KiB per dispatch) into HBM bytes per launch of the FP32
-    D2Q37 step kernels, each counter scaled by what it reads for the
-    arithmetic-free stream kernel of known size (74 FP32 planes read and
-    written once), and store them with the kernel source hash."""
+    WRITE_SIZE, KiB per dispatch) into HBM bytes per launch of the FP32 step
+    kernels of one lattice, per launch shape (layout, cache policy,
+    work-group size, cells per work-item), each counter scaled by what it
+    reads for the arithmetic-free stream kernel of known size (74 FP32 planes
+    of 2^24 cells read and written once), and store them with the kernel
+    source hash."""
+    import re
     fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
-    ref = ("k_stream_rw",)
     known = 74 * ncell * 4
-    sf = np.median(_per_dispatch(fr, "FETCH_SIZE", ref)) * 1024 / known
-    sw = np.median(_per_dispatch(wr, "WRITE_SIZE", ref)) * 1024 / known
-    bpl = bytes_per_cell(37, 2, "f32") * ncell
+
+    def median_all(groups):
+        return np.median([v for vals in groups.values() for v in vals])
+
+    sf = median_all(_per_dispatch(fr, "FETCH_SIZE", ("k_stream_rw",))) * 1024 / known
+    sw = median_all(_per_dispatch(wr, "WRITE_SIZE", ("k_stream_rw",))) * 1024 / known
+    Q = int(lattice.split("Q")[1])
+    bpl = bytes_per_cell(Q, 2, "f32") * ncell
+    pat = re.compile(r"k_step<esbgk::Lat" + lattice + r", 0, (\d), true, (\d),")
+    fd = _per_dispatch(fr, "FETCH_SIZE", (f"k_step<esbgk::Lat{lattice}, 0, ",))
+    wd = _per_dispatch(wr, "WRITE_SIZE", (f"k_step<esbgk::Lat{lattice}, 0, ",))
     kernels = {}
-    for name, prefix in STEP_KERNELS.items():
-        fd = _per_dispatch(fr, "FETCH_SIZE", (prefix,), ncell)
-        wd = _per_dispatch(wr, "WRITE_SIZE", (prefix,), ncell)
-        if not fd or not wd:
+    for g in sorted(set(fd) & set(wd), key=str):
+        m = pat.search(g[0])
+        if not m or ncell % g[1]:
             continue
-        f, w = np.median(fd) * 1024, np.median(wd) * 1024
-        kernels[name] = {"fetch_bytes_raw": f, "write_bytes_raw": w, "dispatches": [len(fd), len(wd)],
-                         "hbm_bytes_per_launch": f / sf + w / sw,
-                         "traffic_over_algorithmic": (f / sf + w / sw) / bpl}
-    res = {"workload": "D2Q37 4096x4096 FP32 f+g", "algorithmic_bytes_per_launch": bpl,
+        key = traffic_key(LAYOUT_NAMES[int(m.group(1))], int(m.group(2)), g[2], ncell // g[1])
+        f, w = np.median(fd[g]) * 1024, np.median(wd[g]) * 1024
+        kernels[key] = {"fetch_bytes_raw": f, "write_bytes_raw": w, "dispatches": [len(fd[g]), len(wd[g])],
+                        "hbm_bytes_per_launch": f / sf + w / sw,
+                        "traffic_over_algorithmic": (f / sf + w / sw) / bpl}
+    variant = "aa" if lattice == "D2Q37" else "d3q39"
+    workload = "D2Q37 4096x4096" if lattice == "D2Q37" else "D3Q39 256x256x256"
+    res = {"workload": f"{workload} FP32 f+g", "algorithmic_bytes_per_launch": bpl,
+           "key": "layout, cache-policy template argument (0 default, 2 non-temporal loads and stores, "
+                  "3 non-temporal stores), work-group size, cells per work-item",
            "stream_kernel_fetch_factor": sf, "stream_kernel_write_factor": sw, "kernels": kernels,
            "kernel_source_hash": kernel_source_hash(),
            "commands": [f"rocprofv3 --pmc FETCH_SIZE -d {fetch_dir} -- python3 bench.py --steps 6 --warmup 2 "
-                        "--variants aa --no-cpu",
+                        f"--variants {variant} --no-cpu",
                         f"rocprofv3 --pmc WRITE_SIZE -d {write_dir} -- python3 bench.py --steps 6 --warmup 2 "
-                        "--variants aa --no-cpu",
-                        f"python bench.py --ingest-counters {fetch_dir} {write_dir}"]}
-    with open(PROFILE_TRAFFIC, "w") as fh:
+                        f"--variants {variant} --no-cpu",
+                        f"python bench.py --ingest-counters {fetch_dir} {write_dir} --lattice {lattice}"]}
+    with open(traffic_path(lattice), "w") as fh:
         json.dump(res, fh, indent=1)
-    print(json.dumps(res, indent=1))
+    print(json.dumps({k: round(v["traffic_over_algorithmic"], 4) for k, v in kernels.items()}, indent=1))
 
 
 def _oracle_rate(n, threads, seconds, max_steps):
@@ -218,9 +255,11 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--lattice", default="D2Q37", choices=("D2Q37", "D3Q39"),
+                    help="lattice whose step kernels --ingest-counters summarises")
     args = ap.parse_args()
     if args.ingest_counters:
-        ingest_counters(*args.ingest_counters)
+        ingest_counters(*args.ingest_counters, lattice=args.lattice)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: the library runs on one GPU only (the batched and single-domain paths have no "
@@ -243,7 +282,7 @@ def main():
 
     # headline: two-copy pull streaming, FP32
     main_run = time_single(esb, torch, D, Q, Nf, Pr, tau, (N, N), "f32", fields, args.steps, args.warmup, tune_cache)
-    roof = roofline(bpl, main_run["launch_ms"], traffic=measured_traffic("pull"))
+    roof = roofline(bpl, main_run["launch_ms"], traffic=pull_traffic(main_run["tile"]))
     roof["kernel"] = "k_step<D2Q37, FP32, pull layout> (the one kernel of every step)"
     roof["bytes_per_launch"] = bpl
     roof["avg_launch_ms"] = round(main_run["launch_ms"], 4)
@@ -283,10 +322,10 @@ def main():
             "mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / args.steps, 4),
             "even_kernel": {"avg_launch_ms": round(r["even_ms"], 4),
                             "frac_of_hbm_peak": round(bpl / (r["even_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                            "traffic": measured_traffic("aa_even")},
+                            "traffic": measured_traffic("aa_even", r["tile"][0])},
             "odd_kernel": {"avg_launch_ms": round(r["odd_ms"], 4),
                            "frac_of_hbm_peak": round(bpl / (r["odd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "traffic": measured_traffic("aa_odd")},
+                           "traffic": measured_traffic("aa_odd", r["tile"][1])},
             "tile": r["tile"]}
         del r
         torch.cuda.empty_cache()
@@ -323,6 +362,7 @@ def main():
         var["d3q39_256cube_f32"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / s3, 4),
                                     "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                     "GBs_per_step": round(b / (r["total_ms"] / s3 * 1e-3) / 1e9, 1),
+                                    "traffic": pull_traffic(r["tile"], "D3Q39"),
                                     "streaming": "pull", "tile": r["tile"]}
         del r
         torch.cuda.empty_cache()
