@@ -7,8 +7,9 @@ stream-collide launch over the whole grid with inputs resident in HBM, in the
 two-copy pull streaming scheme.  `value` is million lattice-cell updates per
 second (MLUPS) over exactly --steps timed steps.  Variants (the same workload
 with A-A in-place streaming, FP16/BF16 deviation storage, D3Q39 at 256^3,
-the batched 256-domain workload in its execution modes) are reported beside
-it, each with its HBM-roofline fraction.
+D2Q33, the batched 256-domain workload in its execution modes and both
+streaming schemes) are reported beside it, each with its HBM-roofline
+fraction.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--variants aa,f16,bf16,d3q39,batch]
                     [--no-variants] [--no-cpu]
@@ -387,7 +388,10 @@ def main():
         del r, f2
         torch.cuda.empty_cache()
     if "batch" in variants:
-        var["batched_256_d2q37_f32"] = time_batch(esb, torch, workloads, args.batch_steps, tune_cache)
+        var["batched_256_d2q37_f32"] = time_batch(esb, torch, workloads, args.batch_steps, tune_cache, "pull")
+        torch.cuda.empty_cache()
+        var["batched_256_d2q37_f32_aa"] = time_batch(esb, torch, workloads, args.batch_steps, tune_cache, "aa",
+                                                     grouped=True)
         torch.cuda.empty_cache()
     if var:
         out["variants"] = var
@@ -405,18 +409,19 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def time_batch(esb, torch, workloads, batch_steps, tune_cache):
-    """256 independent domains (A-A in place) in the three execution modes
-    with the autotuned launch shape, plus the persistent launch advancing
-    MALL-sized domain groups."""
+def time_batch(esb, torch, workloads, batch_steps, tune_cache, streaming="pull", grouped=False):
+    """256 independent domains (two-copy pull or A-A in place) in the three
+    execution modes with the autotuned launch shape, and optionally the
+    persistent launch advancing MALL-sized domain groups."""
     doms = workloads.batch_domains(256)
-    bt = esb.Batch(2, 37, [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms])
+    bt = esb.Batch(2, 37, [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms],
+                   streaming=streaming)
     for k, d in enumerate(doms):
         bt.init_fields(k, *workloads.batch_fields(d))
     cells, bps = bt.info()
     block, policy = bt.autotune(cache_path=tune_cache)
-    log(f"batch autotune: block {block}, policy {policy}")
-    res = {"tile": {"block": block, "policy": policy}}
+    log(f"batch ({streaming}) autotune: block {block}, policy {policy}")
+    res = {"streaming": streaming, "tile": {"block": block, "policy": policy}}
 
     def run(name, mode, n):
         bt.step(n if mode != 2 else 20, mode)          # warm-up (captures the graph of n steps)
@@ -429,26 +434,28 @@ def time_batch(esb, torch, workloads, batch_steps, tune_cache):
                      "frac_of_hbm_peak": round(bps * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     for mode, name in ((0, "persistent_graph"), (1, "graph_per_step")):
-        log(f"batch {len(doms)} domains, {cells} cells: mode {name}, {batch_steps} steps")
+        log(f"batch ({streaming}) {len(doms)} domains, {cells} cells: mode {name}, {batch_steps} steps")
         run(name, mode, batch_steps)
     # the per-domain loop at its own best work-group size (the tuned shape of
     # the persistent launch need not suit one launch per domain)
     best = None
     for blk, pol in sorted({(256, 0), (512, 0), (block, policy)}):
         bt.set_tile(blk, pol)
-        log(f"batch {len(doms)} domains: mode per_domain_loop, block {blk} policy {pol}, {batch_steps} steps")
+        log(f"batch ({streaming}) {len(doms)} domains: mode per_domain_loop, block {blk} policy {pol}, "
+            f"{batch_steps} steps")
         run("per_domain_loop", 2, batch_steps)
         r = res.pop("per_domain_loop")
         if best is None or r["mlups"] > best["mlups"]:
             best = dict(r, tile={"block": blk, "policy": pol})
     res["per_domain_loop"] = best
-    # the same persistent launch, advancing groups of domains (about 128 MB
-    # of storage each) eight steps at a time while they sit in the MALL
-    bt.set_tile(block, policy, 8, 128e6)
-    ng = max(8, batch_steps // 5)
-    log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {ng} steps")
-    run("persistent_graph_grouped", 0, ng)
-    res["persistent_graph_grouped"].update(window=8, group_bytes=128e6)
+    if grouped:
+        # the same persistent launch, advancing groups of domains (about 128
+        # MB of storage each) eight steps at a time while they sit in the MALL
+        bt.set_tile(block, policy, 8, 128e6)
+        ng = max(8, batch_steps // 5)
+        log(f"batch: persistent, domain groups of 128 MB advanced 8 steps at a time, {ng} steps")
+        run("persistent_graph_grouped", 0, ng)
+        res["persistent_graph_grouped"].update(window=8, group_bytes=128e6)
     res["cells"] = cells
     res["domains"] = len(doms)
     res["speedup_vs_per_domain_loop"] = round(res["persistent_graph"]["mlups"] / res["per_domain_loop"]["mlups"], 3)

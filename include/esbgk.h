@@ -275,7 +275,10 @@ typedef struct {
 
 /* Create a batch of n domains of lattice (D, Q).  The library allocates all
  * storage in one device buffer and its own HIP stream.  Same validation per
- * domain as esbgk_create. */
+ * domain as esbgk_create.  storage is ESBGK_F32, ESBGK_F16_DEV or
+ * ESBGK_BF16_DEV, or-ed with ESBGK_PULL for two-copy pull streaming (both
+ * copies of a domain side by side; twice the memory, bitwise the same
+ * results as A-A in place). */
 int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int storage, esbgk_batch_t **out);
 
 /* Route the batch's work to hip_stream (non-NULL; graphs are captured on it). */
@@ -290,7 +293,12 @@ int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const do
  * by grid-wide barriers; launched through a captured HIP graph);
  * mode 1: one launch per step covering every domain; mode 2: one launch per
  * domain per step (the per-domain loop baseline).  All modes give bitwise
- * identical results. */
+ * identical results.  A mode-0 launch fills the GPU with work-groups that
+ * must all be resident at once: the library orders it after the previous
+ * mode-0 launch of any batch in the process on the same device, and work
+ * on other streams only delays it, but a kernel elsewhere that holds
+ * compute units for longer than about a second makes its barrier wait
+ * time out (see esbgk_batch_status). */
 int esbgk_batch_step(esbgk_batch_t *b, int64_t n, int mode);
 
 /* Launch shape of the batched kernels: block = cells per tile and work-group

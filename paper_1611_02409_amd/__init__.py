@@ -176,10 +176,12 @@ class Lattice:
         if kappa != 0.2:
             self.set_kappa(kappa)
 
-    def __del__(self):
+    # the destroy function is bound at definition: module globals may already
+    # be cleared when the interpreter collects handles at exit
+    def __del__(self, _destroy=_lib.esbgk_destroy):
         h = getattr(self, "_h", None)
         if h:
-            _lib.esbgk_destroy(h)
+            _destroy(h)
             self._h = None
 
     @property
@@ -327,10 +329,10 @@ PERSISTENT, PER_STEP, PER_DOMAIN = 0, 1, 2
 class Batch:
     """Independent periodic domains of one lattice and storage mode, stepped
     together.  `domains` is a list of dicts with keys dims, Nf, Pr, tau and
-    optionally kappa."""
+    optionally kappa; streaming "aa" (in place) or "pull" (two copies)."""
 
-    def __init__(self, D: int, Q: int, domains, storage: str = "f32"):
-        self.D, self.Q, self.storage = D, Q, storage
+    def __init__(self, D: int, Q: int, domains, storage: str = "f32", streaming: str = "aa"):
+        self.D, self.Q, self.storage, self.streaming = D, Q, storage, streaming
         self.domains = [dict(d) for d in domains]
         arr = (DomainDesc * len(domains))()
         for i, d in enumerate(domains):
@@ -339,13 +341,13 @@ class Batch:
                                 (ctypes.c_int64 * 3)(*dims))
         h = _vp()
         self._h = None
-        _check(_lib.esbgk_batch_create(D, Q, len(domains), arr, STORAGE[storage], ctypes.byref(h)))
+        _check(_lib.esbgk_batch_create(D, Q, len(domains), arr, _storage_code(storage, streaming), ctypes.byref(h)))
         self._h = h
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.esbgk_batch_destroy):
         h = getattr(self, "_h", None)
         if h:
-            _lib.esbgk_batch_destroy(h)
+            _destroy(h)
             self._h = None
 
     def _shape(self, k):

@@ -6,6 +6,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -36,6 +37,7 @@ using namespace esbgk;
 
 struct esbgk_batch {
     int D = 0, Q = 0, storage = 0, n = 0;
+    bool pull = false;   // two-copy pull layout (else A-A in place)
     std::vector<DomainSetup> su;
     std::vector<esbgk_domain_desc> desc;
     std::vector<uint64_t> f_off, g_off;
@@ -61,8 +63,11 @@ struct esbgk_batch {
     // captured graphs keyed by (mode, n, parity, block, policy, window)
     std::map<std::tuple<int, int64_t, int, int, int, uint32_t>, hipGraphExec_t> graphs;
 
-    char *fb(int k) const { return buf + f_off[k]; }
-    char *gb(int k) const { return su[k].npop == 2 ? buf + g_off[k] : nullptr; }
+    // storage of domain k's state after s steps (pull: copy s % 2)
+    uint64_t copy_at(int k, int64_t s) const { return pull && (s & 1) ? su[k].copy_bytes : 0; }
+    char *fb(int k) const { return buf + f_off[k] + copy_at(k, steps); }
+    char *gb(int k) const { return su[k].npop == 2 ? buf + g_off[k] + copy_at(k, steps) : nullptr; }
+    int lay() const { return pull ? LAY_PULL : (steps & 1) ? LAY_ODD : LAY_EVEN; }
 };
 
 namespace {
@@ -104,6 +109,7 @@ int build_tables(esbgk_batch_t *b) {
         DomDev &dd = doms[k];
         dd.f_off = b->f_off[k];
         dd.g_off = b->g_off[k];
+        dd.copy_off = b->pull ? s.copy_bytes : 0;
         dd.pb = (uint32_t)s.plane_bytes;
         dd.sb = (uint32_t)(s.plane_bytes * b->Q);
         dd.ntiles = nt;
@@ -161,16 +167,22 @@ void enqueue(esbgk_batch_t *b, int64_t n, int mode, uint32_t grid) {
         t.block = b->block;
         t.policy = b->policy;
         for (int64_t s = 0; s < n; s++) {
-            const bool odd = ((b->steps + s) & 1) != 0;
-            for (int k = 0; k < b->n; k++)
-                b->ops->step(b->fb(k), b->gb(k), b->fb(k), b->gb(k), (uint32_t)b->su[k].plane_bytes,
-                             (uint32_t)(b->su[k].plane_bytes * b->Q), b->su[k].geom, b->su[k].coll,
-                             odd ? LAY_ODD : LAY_EVEN, b->su[k].npop == 2, t, b->stream);
+            const int64_t at = b->steps + s;
+            const int lay = b->pull ? LAY_PULL : (at & 1) ? LAY_ODD : LAY_EVEN;
+            for (int k = 0; k < b->n; k++) {
+                const DomainSetup &su = b->su[k];
+                char *rf = b->buf + b->f_off[k] + b->copy_at(k, at);
+                char *wf = b->buf + b->f_off[k] + b->copy_at(k, at + 1);
+                char *rg = su.npop == 2 ? b->buf + b->g_off[k] + b->copy_at(k, at) : nullptr;
+                char *wg = su.npop == 2 ? b->buf + b->g_off[k] + b->copy_at(k, at + 1) : nullptr;
+                b->ops->step(rf, rg, wf, wg, (uint32_t)su.plane_bytes, (uint32_t)(su.plane_bytes * b->Q), su.geom,
+                             su.coll, lay, su.npop == 2, t, b->stream);
+            }
         }
     } else if (mode == 1) {
         for (int64_t s = 0; s < n; s++)
             b->bops->step(b->buf, b->d_doms, b->d_tile_dom, b->d_tile_cell, b->tiles, b->block,
-                          ((b->steps + s) & 1) != 0, b->policy, b->stream);
+                          ((b->steps + s) & 1) != 0, b->policy, b->pull, b->stream);
     } else {
         k_batch_reset<<<1, 64, 0, b->stream>>>(b->d_ctr);
         BatchDev bd{};
@@ -186,13 +198,13 @@ void enqueue(esbgk_batch_t *b, int64_t n, int mode, uint32_t grid) {
         bd.arrive = b->d_ctr;
         bd.status = b->d_ctr + 1;
         bd.claim = b->d_ctr + 2;
-        b->bops->persistent(b->buf, bd, grid, b->block, b->policy, b->stream);
+        b->bops->persistent(b->buf, bd, grid, b->block, b->policy, b->pull, b->stream);
     }
 }
 
 int persistent_grid(esbgk_batch_t *b, uint32_t *grid) {
     int per_cu = 0;
-    if (b->bops->occupancy(b->block, b->policy, &per_cu) || per_cu < 1) {
+    if (b->bops->occupancy(b->block, b->policy, b->pull, &per_cu) || per_cu < 1) {
         set_error("occupancy query failed for block %d", b->block);
         return ESBGK_EDEVICE;
     }
@@ -201,6 +213,23 @@ int persistent_grid(esbgk_batch_t *b, uint32_t *grid) {
     ESBGK_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     *grid = (uint32_t)(per_cu * ncu);
     return ESBGK_OK;
+}
+
+// A persistent launch needs all of its work-groups resident at once (they
+// meet at grid-wide barriers), so two of them must never run at the same
+// time: another batch's persistent kernel on another stream would hold the
+// compute units one of them waits for.  Every mode-0 call therefore orders
+// its launch after the previous one issued in this process on the same
+// device: its stream waits on an event recorded behind that launch.  The
+// events live until the process ends.
+struct PersistentOrder {
+    std::mutex m;
+    std::map<int, hipEvent_t> last;   // device -> event after its last persistent launch
+};
+
+PersistentOrder &persistent_order() {
+    static PersistentOrder o;
+    return o;
 }
 
 }  // namespace
@@ -214,9 +243,10 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
         return ESBGK_EINVAL;
     }
     *out = nullptr;
-    if (storage & ESBGK_PULL) {
-        set_error("the batched path keeps the A-A in-place layout (ESBGK_PULL is for single-domain handles)");
-        return ESBGK_EUNSUPPORTED;
+    const int codec = storage & ~ESBGK_PULL;
+    if (codec < 0 || codec > 2) {
+        set_error("unknown storage mode %d", storage);
+        return ESBGK_EINVAL;
     }
     auto *b = new (std::nothrow) esbgk_batch();
     if (!b) {
@@ -226,6 +256,7 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
     b->D = D;
     b->Q = Q;
     b->storage = storage;
+    b->pull = (storage & ESBGK_PULL) != 0;
     b->n = n;
     b->su.resize(n);
     b->desc.assign(desc, desc + n);
@@ -249,8 +280,8 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
         off += b->su[k].bytes;
     }
     b->bytes = off;
-    b->ops = get_ops(D, Q, storage);
-    b->bops = get_batch_ops(D, Q, storage);
+    b->ops = get_ops(D, Q, codec);
+    b->bops = get_batch_ops(D, Q, codec);
     int rc = ESBGK_OK;
     do {
         hipError_t e = hipStreamCreate(&b->stream);
@@ -315,7 +346,7 @@ int esbgk_batch_init_fields(esbgk_batch_t *b, int k, const double *rho, const do
     hipError_t e = hipMemcpyAsync(tmp, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess) {
         b->ops->init(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * b->Q), s.geom, s.coll,
-                     (const float *)tmp, LAY_EVEN, s.npop == 2, b->stream);
+                     (const float *)tmp, b->pull ? LAY_PULL : LAY_EVEN, s.npop == 2, b->stream);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     }
@@ -391,7 +422,19 @@ int esbgk_batch_step(esbgk_batch_t *b, int64_t n, int mode) {
         }
         it = b->graphs.emplace(key, ge).first;
     }
-    ESBGK_HIP(hipGraphLaunch(it->second, b->stream));
+    if (mode == 0) {
+        int dev = 0;
+        ESBGK_HIP(hipGetDevice(&dev));
+        PersistentOrder &po = persistent_order();
+        std::lock_guard<std::mutex> lock(po.m);
+        hipEvent_t &ev = po.last[dev];
+        if (!ev) ESBGK_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ESBGK_HIP(hipStreamWaitEvent(b->stream, ev, 0));
+        ESBGK_HIP(hipGraphLaunch(it->second, b->stream));
+        ESBGK_HIP(hipEventRecord(ev, b->stream));
+    } else {
+        ESBGK_HIP(hipGraphLaunch(it->second, b->stream));
+    }
     b->steps += n;
     return ESBGK_OK;
 }
@@ -470,7 +513,7 @@ int esbgk_batch_read_moments(esbgk_batch_t *b, int k, double *rho, double *u, do
     float *tmp = nullptr;
     ESBGK_HIP(hipMalloc(&tmp, planes * n * sizeof(float)));
     b->ops->moments(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * b->Q), s.geom, s.coll,
-                    (b->steps & 1) ? LAY_ODD : LAY_EVEN, s.npop == 2, tmp, P != nullptr, b->stream);
+                    b->lay(), s.npop == 2, tmp, P != nullptr, b->stream);
     std::vector<float> host;
     if (int rc = host_buffer(host, planes * n)) return rc;
     hipError_t e = hipGetLastError();
@@ -512,7 +555,7 @@ int esbgk_batch_totals(esbgk_batch_t *b, int k, double *out) {
     if (e == hipSuccess) {
         b->ops->plane_sums(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * b->Q),
                            s.geom.ncell, b->Q, s.npop == 2, part, nchunks, b->stream);
-        launch_totals_final(part, nchunks, s.lc, s.npop, (b->steps & 1) != 0, s.geom.ncell,
+        launch_totals_final(part, nchunks, s.lc, s.npop, b->lay() == LAY_ODD, s.geom.ncell,
                             0.5 * b->desc[k].N_f, tot, b->stream);
         e = hipGetLastError();
         if (e == hipSuccess) e = hipMemcpyAsync(out, tot, sizeof(double) * (2 + b->D), hipMemcpyDeviceToHost, b->stream);
@@ -540,7 +583,7 @@ int esbgk_batch_read_populations(esbgk_batch_t *b, int k, double *f, double *g) 
     float *tmp = nullptr;
     ESBGK_HIP(hipMalloc(&tmp, n * Q * npop * sizeof(float)));
     b->ops->cells(b->fb(k), b->gb(k), (uint32_t)s.plane_bytes, (uint32_t)(s.plane_bytes * Q), s.geom, s.coll,
-                  (b->steps & 1) ? LAY_ODD : LAY_EVEN, npop == 2, nullptr, (uint32_t)n, tmp, b->stream);
+                  b->lay(), npop == 2, nullptr, (uint32_t)n, tmp, b->stream);
     std::vector<float> host;
     if (int rc = host_buffer(host, n * Q * npop)) return rc;
     hipError_t e = hipGetLastError();

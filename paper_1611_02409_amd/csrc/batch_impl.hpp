@@ -23,6 +23,7 @@ namespace esbgk {
 
 struct DomDev {
     uint64_t f_off, g_off;   // byte offsets of the f and g sets in the batch buffer
+    uint64_t copy_off;       // two-copy pull layout: bytes from copy 0 to copy 1
     uint32_t pb, sb;         // bytes per plane / per set
     uint32_t ntiles;         // tiles per step
     uint32_t has_g;
@@ -67,38 +68,48 @@ __device__ __forceinline__ T uniform_load(const T *p) {
 
 __device__ __forceinline__ uint32_t uniform_u32(const uint32_t *p) { return __builtin_amdgcn_readfirstlane(*p); }
 
-// Process one tile of one domain at the given parity.
-template <class L, int S, int CP, bool ODD, bool HAS_G>
+// Process one tile of one domain at the given parity of the step count.
+// A-A (PULL false): in place, even or odd layout.  Two-copy pull: the state
+// of an even step count is in copy 0 and the step writes copy 1, and the
+// other way round on odd counts.
+template <class L, int S, int CP, bool ODD, bool HAS_G, bool PULL>
 __device__ __forceinline__ void tile_step(char *base, const DomDev &dd, uint32_t cell) {
     if (cell >= dd.geom.ncell) return;
     Nbr<L, kElemBytes<S, HAS_G>> nb;
-    if constexpr (ODD) nb.init(cell, dd.geom);
+    if constexpr (ODD || PULL) nb.init(cell, dd.geom);
     else nb.own = cell * kElemBytes<S, HAS_G>;
-    const Sets R(base + dd.f_off, HAS_G ? base + dd.g_off : nullptr, dd.pb, dd.sb);
+    const uint64_t rd = PULL && ODD ? dd.copy_off : 0, wr = PULL && !ODD ? dd.copy_off : 0;
+    const Sets R(base + dd.f_off + rd, HAS_G ? base + dd.g_off + rd : nullptr, dd.pb, dd.sb);
     float F[L::Q], E[HAS_G ? L::Q : 1];
-    gather<L, S, ODD, HAS_G, load_aux(CP)>(R, nb, F, E);
+    constexpr int LAY = PULL ? LAY_PULL : ODD ? LAY_ODD : LAY_EVEN;
+    gather<L, S, LAY, HAS_G, load_aux(CP)>(R, nb, F, E);
     collide<L, HAS_G, TargetReal<S>>(dd.coll, F, E);
-    scatter<L, S, ODD, HAS_G, store_aux(CP)>(R, nb, F, E);
+    if constexpr (PULL) {
+        const Sets W(base + dd.f_off + wr, HAS_G ? base + dd.g_off + wr : nullptr, dd.pb, dd.sb);
+        scatter<L, S, LAY, HAS_G, store_aux(CP)>(W, nb, F, E);
+    } else {
+        scatter<L, S, LAY, HAS_G, store_aux(CP)>(R, nb, F, E);
+    }
 }
 
-template <class L, int S, int CP>
+template <class L, int S, int CP, bool PULL>
 __device__ __forceinline__ void tile_dispatch(char *base, const DomDev &dd, uint32_t cell, bool odd) {
     if (odd) {
-        if (dd.has_g) tile_step<L, S, CP, true, true>(base, dd, cell);
-        else tile_step<L, S, CP, true, false>(base, dd, cell);
+        if (dd.has_g) tile_step<L, S, CP, true, true, PULL>(base, dd, cell);
+        else tile_step<L, S, CP, true, false, PULL>(base, dd, cell);
     } else {
-        if (dd.has_g) tile_step<L, S, CP, false, true>(base, dd, cell);
-        else tile_step<L, S, CP, false, false>(base, dd, cell);
+        if (dd.has_g) tile_step<L, S, CP, false, true, PULL>(base, dd, cell);
+        else tile_step<L, S, CP, false, false, PULL>(base, dd, cell);
     }
 }
 
 // One launch per step: block b processes tile b.
-template <class L, int S, int CP>
+template <class L, int S, int CP, bool PULL>
 __global__ __launch_bounds__(512) void k_batch_step(char *base, const DomDev *doms, const uint32_t *tile_dom,
                                                     const uint32_t *tile_cell, uint32_t odd) {
     const uint32_t t = blockIdx.x;
     const DomDev dd = uniform_load(doms + uniform_u32(tile_dom + t));
-    tile_dispatch<L, S, CP>(base, dd, uniform_u32(tile_cell + t) + threadIdx.x, odd != 0);
+    tile_dispatch<L, S, CP, PULL>(base, dd, uniform_u32(tile_cell + t) + threadIdx.x, odd != 0);
 }
 
 // Grid-wide barrier number `round` (0-based) of a launch with `nblocks`
@@ -132,7 +143,7 @@ __device__ __forceinline__ bool grid_barrier(const BatchDev &b, uint32_t round, 
     return *sh_abort == 0;
 }
 
-template <class L, int S, int CP>
+template <class L, int S, int CP, bool PULL>
 __device__ __forceinline__ void persistent_body(char *base, const BatchDev &b) {
     __shared__ uint32_t sh_abort, sh_t;
     if (threadIdx.x == 0) sh_abort = 0;
@@ -159,7 +170,7 @@ __device__ __forceinline__ void persistent_body(char *base, const BatchDev &b) {
                     if (k >= nt) break;
                     const uint32_t t = tb + k;
                     const DomDev dd = uniform_load(b.doms + uniform_u32(b.tile_dom + t));
-                    tile_dispatch<L, S, CP>(base, dd, uniform_u32(b.tile_cell + t) + threadIdx.x, odd);
+                    tile_dispatch<L, S, CP, PULL>(base, dd, uniform_u32(b.tile_cell + t) + threadIdx.x, odd);
                 }
                 first += nt + G;
                 if (!grid_barrier(b, round++, G, &sh_abort)) return;
@@ -171,47 +182,57 @@ __device__ __forceinline__ void persistent_body(char *base, const BatchDev &b) {
 // Register budget: three waves per SIMD where the code fits in 168 VGPRs
 // without spilling (BF16); FP32 storage (FP64 target) and FP16 storage keep
 // the compiler's choice.
-template <class L, int S, int CP>
+template <class L, int S, int CP, bool PULL>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(S == ST_BF16 && L::Q <= 37 ? 3 : 1))) void k_batch_persistent(
     char *base, BatchDev b) {
-    persistent_body<L, S, CP>(base, b);
+    persistent_body<L, S, CP, PULL>(base, b);
 }
 
-template <class L, int S, int CP>
+template <class L, int S, int CP, bool PULL>
 __global__ __launch_bounds__(512) void k_batch_persistent_f16(char *base, BatchDev b) {
-    persistent_body<L, S, CP>(base, b);
+    persistent_body<L, S, CP, PULL>(base, b);
 }
 
+// policy: 0 default, 1 non-temporal loads and stores, 2 non-temporal stores;
+// pull: two-copy pull layout (else A-A in place)
 struct BatchOps {
     void (*step)(char *base, const DomDev *doms, const uint32_t *tile_dom, const uint32_t *tile_cell, uint32_t tiles,
-                 int block, bool odd, int policy, hipStream_t s);
-    void (*persistent)(char *base, const BatchDev &b, uint32_t grid, int block, int policy, hipStream_t s);
-    int (*occupancy)(int block, int policy, int *blocks_per_cu);
+                 int block, bool odd, int policy, bool pull, hipStream_t s);
+    void (*persistent)(char *base, const BatchDev &b, uint32_t grid, int block, int policy, bool pull,
+                       hipStream_t s);
+    int (*occupancy)(int block, int policy, bool pull, int *blocks_per_cu);
 };
 
 template <class L, int S>
 struct BatchOpsImpl {
+    template <int CP, bool PULL>
+    static void step_k(char *base, const DomDev *doms, const uint32_t *tile_dom, const uint32_t *tile_cell,
+                       uint32_t tiles, int block, bool odd, hipStream_t s) {
+        k_batch_step<L, S, CP, PULL><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
+    }
     static void step(char *base, const DomDev *doms, const uint32_t *tile_dom, const uint32_t *tile_cell,
-                     uint32_t tiles, int block, bool odd, int policy, hipStream_t s) {
-        if (policy == 1) k_batch_step<L, S, 2><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
-        else if (policy == 2) k_batch_step<L, S, 3><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
-        else k_batch_step<L, S, 0><<<tiles, block, 0, s>>>(base, doms, tile_dom, tile_cell, odd ? 1u : 0u);
+                     uint32_t tiles, int block, bool odd, int policy, bool pull, hipStream_t s) {
+        auto k = pull ? (policy == 1 ? &step_k<2, true> : policy == 2 ? &step_k<3, true> : &step_k<0, true>)
+                      : (policy == 1 ? &step_k<2, false> : policy == 2 ? &step_k<3, false> : &step_k<0, false>);
+        k(base, doms, tile_dom, tile_cell, tiles, block, odd, s);
     }
-    template <int CP>
+    template <int CP, bool PULL>
     static auto kernel() {
-        if constexpr (S == ST_F16) return &k_batch_persistent_f16<L, S, CP>;
-        else return &k_batch_persistent<L, S, CP>;
+        if constexpr (S == ST_F16) return &k_batch_persistent_f16<L, S, CP, PULL>;
+        else return &k_batch_persistent<L, S, CP, PULL>;
     }
-    static void persistent(char *base, const BatchDev &b, uint32_t grid, int block, int policy, hipStream_t s) {
-        if (policy == 1) kernel<2>()<<<grid, block, 0, s>>>(base, b);
-        else if (policy == 2) kernel<3>()<<<grid, block, 0, s>>>(base, b);
-        else kernel<0>()<<<grid, block, 0, s>>>(base, b);
+    static auto pick(int policy, bool pull) {
+        return pull ? (policy == 1 ? kernel<2, true>() : policy == 2 ? kernel<3, true>() : kernel<0, true>())
+                    : (policy == 1 ? kernel<2, false>() : policy == 2 ? kernel<3, false>() : kernel<0, false>());
     }
-    static int occupancy(int block, int policy, int *blocks_per_cu) {
-        hipError_t e = policy == 1   ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<2>(), block, 0)
-                       : policy == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<3>(), block, 0)
-                                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, kernel<0>(), block, 0);
-        return e == hipSuccess ? 0 : -1;
+    static void persistent(char *base, const BatchDev &b, uint32_t grid, int block, int policy, bool pull,
+                           hipStream_t s) {
+        pick(policy, pull)<<<grid, block, 0, s>>>(base, b);
+    }
+    static int occupancy(int block, int policy, bool pull, int *blocks_per_cu) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, pick(policy, pull), block, 0) == hipSuccess
+                   ? 0
+                   : -1;
     }
     static constexpr BatchOps ops{&step, &persistent, &occupancy};
 };

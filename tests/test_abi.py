@@ -104,14 +104,22 @@ def test_storage_bytes(esb):
         esb.storage_bytes(2, 37, 3, (64, 64), "f32", "push")
 
 
-def test_batch_rejects_pull_streaming_without_a_device(esb):
+def test_batch_create_validates_before_touching_a_device(esb):
+    """Unknown storage codes and invalid domains (in either streaming
+    scheme) are refused before any device call."""
     lib = esb._lib
-    desc = (esb.DomainDesc * 1)()
-    desc[0].N_f, desc[0].Pr, desc[0].tau, desc[0].kappa = 3, 0.71, 0.6, 0.2
-    desc[0].dims[0], desc[0].dims[1], desc[0].dims[2] = 64, 64, 1
+    desc = (esb.DomainDesc * 2)()
+    for k in range(2):
+        desc[k].N_f, desc[k].Pr, desc[k].tau, desc[k].kappa = 3, 0.71, 0.6, 0.2
+        desc[k].dims[0], desc[k].dims[1], desc[k].dims[2] = 64, 64, 1
+    desc[1].tau = 0.5
     h = ctypes.c_void_p()
-    assert lib.esbgk_batch_create(2, 37, 1, desc, esb.PULL, ctypes.byref(h)) == -2
-    assert "ESBGK_PULL" in lib.esbgk_last_error().decode()
+    assert lib.esbgk_batch_create(2, 37, 2, desc, 3 | esb.PULL, ctypes.byref(h)) == -1
+    assert "storage" in lib.esbgk_last_error().decode()
+    for code in (esb.F32, esb.F32 | esb.PULL, esb.BF16_DEV | esb.PULL):
+        assert lib.esbgk_batch_create(2, 37, 2, desc, code, ctypes.byref(h)) == -1
+        assert lib.esbgk_last_error().decode().startswith("domain 1:")
+        assert not h.value
 
 
 def test_null_handles_are_rejected(esb):

@@ -1,6 +1,7 @@
 """GPU parity of the batched path: every mode (persistent graph launch,
-one launch per step, per-domain launch loop) gives bitwise the same
-populations as single-domain runs, and those match the FP64 oracle."""
+one launch per step, per-domain launch loop), in either streaming scheme
+(A-A in place, two-copy pull), gives bitwise the same populations as
+single-domain runs, and those match the FP64 oracle."""
 import os
 import sys
 
@@ -35,8 +36,8 @@ def fields_of(k, dom):
     return workloads.random_state(dom["dims"], seed=100 + k)
 
 
-def make_batch(storage="f32", block=256, window=1, group_bytes=0.0, policy=0):
-    b = esb.Batch(2, 37, DOMS, storage=storage)
+def make_batch(storage="f32", block=256, window=1, group_bytes=0.0, policy=0, streaming="aa"):
+    b = esb.Batch(2, 37, DOMS, storage=storage, streaming=streaming)
     b.set_tile(block, policy, window, group_bytes)
     for k, d in enumerate(DOMS):
         b.init_fields(k, *fields_of(k, d))
@@ -56,13 +57,14 @@ def same(pa, pb):
     return True
 
 
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
 @pytest.mark.parametrize("nsteps", [1, 6, 7])
-def test_modes_agree_bitwise_and_match_single_domains(nsteps):
-    ref = make_batch()
+def test_modes_agree_bitwise_and_match_single_domains(nsteps, streaming):
+    ref = make_batch(streaming=streaming)
     ref.step(nsteps, mode=esb.PER_DOMAIN)
     p2 = pops(ref)
     for mode in (esb.PER_STEP, esb.PERSISTENT):
-        b = make_batch()
+        b = make_batch(streaming=streaming)
         b.step(nsteps, mode=mode)
         assert b.status() == 0
         assert same(pops(b), p2), f"mode {mode} differs from the per-domain loop"
@@ -76,8 +78,9 @@ def test_modes_agree_bitwise_and_match_single_domains(nsteps):
             assert np.array_equal(g, p2[k][1])
 
 
-def test_batch_matches_oracle():
-    b = make_batch()
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+def test_batch_matches_oracle(streaming):
+    b = make_batch(streaming=streaming)
     b.step(5, mode=esb.PERSISTENT)
     li = esb.lattice_info(2, 37)
     L = oracle.Lattice(2, 37)
@@ -98,27 +101,29 @@ def test_batch_matches_oracle():
         assert abs(t[0] - sim.totals()[0]) / np.prod(d["dims"]) < 1e-7
 
 
-@pytest.mark.parametrize("block,window,group_bytes,policy", [(64, 3, 2e6, 0), (512, 1, 0.0, 2), (128, 16, 1e5, 3),
-                                                              (256, 1, 0.0, 3)])
-def test_persistent_windows_and_groups(block, window, group_bytes, policy):
+@pytest.mark.parametrize("block,window,group_bytes,policy,streaming",
+                         [(64, 3, 2e6, 0, "aa"), (512, 1, 0.0, 2, "aa"), (128, 16, 1e5, 3, "aa"), (256, 1, 0.0, 3, "aa"),
+                          (64, 3, 2e6, 2, "pull"), (512, 1, 0.0, 3, "pull"), (128, 16, 1e5, 0, "pull")])
+def test_persistent_windows_and_groups(block, window, group_bytes, policy, streaming):
     """Domain groups advanced several steps at a time (and tiny groups,
     one domain each), under each cache policy, give the same result as
     step-by-step execution."""
     ref = make_batch()
     ref.step(9, mode=esb.PER_DOMAIN)
-    b = make_batch(block=block, window=window, group_bytes=group_bytes, policy=policy)
+    b = make_batch(block=block, window=window, group_bytes=group_bytes, policy=policy, streaming=streaming)
     b.step(9, mode=esb.PERSISTENT)
     assert b.status() == 0
     assert same(pops(b), pops(ref))
 
 
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
 @pytest.mark.parametrize("mode", [esb.PERSISTENT, esb.PER_STEP])
-def test_graph_replays(mode):
+def test_graph_replays(mode, streaming):
     """The same captured graph replayed several times, with reads in
     between, continues exactly like one long per-domain run."""
     ref = make_batch()
     ref.step(12, mode=esb.PER_DOMAIN)
-    b = make_batch()
+    b = make_batch(streaming=streaming)
     for _ in range(3):
         b.step(4, mode=mode)
         b.read_moments(0)
@@ -126,9 +131,10 @@ def test_graph_replays(mode):
     assert same(pops(b), pops(ref))
 
 
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
 @pytest.mark.parametrize("storage", ["f16", "bf16"])
-def test_reduced_storage_batch_equals_single(storage):
-    b = make_batch(storage=storage)
+def test_reduced_storage_batch_equals_single(storage, streaming):
+    b = make_batch(storage=storage, streaming=streaming)
     b.step(5, mode=esb.PERSISTENT)
     for k, d in enumerate(DOMS[:3]):
         lat = esb.Lattice(2, 37, d["Nf"], d["Pr"], d["tau"], d["dims"], storage=storage)
@@ -145,14 +151,14 @@ def test_init_after_step_is_rejected():
         b.init_fields(0, *fields_of(0, DOMS[0]))
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_autotune_restores_state_and_caches(tmp_path, storage):
+@pytest.mark.parametrize("storage,streaming", [("f32", "aa"), ("bf16", "aa"), ("f32", "pull")])
+def test_autotune_restores_state_and_caches(tmp_path, storage, streaming):
     """The batch autotuner times launch shapes on the batch's own state and
     puts it back bitwise; results after it equal those of an untuned batch;
     a second call takes the cached shape."""
     cache = str(tmp_path / "tune.txt")
-    a = make_batch(storage)
-    b = make_batch(storage)
+    a = make_batch(storage, streaming=streaming)
+    b = make_batch(storage, streaming=streaming)
     a.step(3)
     b.step(3)
     before = pops(a)
@@ -165,7 +171,7 @@ def test_autotune_restores_state_and_caches(tmp_path, storage):
     with open(cache) as fh:
         lines = fh.read().splitlines()
     assert len(lines) == 1 and lines[0].endswith(f"block {blk} policy {pol}")
-    c = make_batch(storage, block=64)
+    c = make_batch(storage, block=64, streaming=streaming)
     assert c.autotune(cache_path=cache) == (blk, pol)
     with open(cache) as fh:
         assert len(fh.read().splitlines()) == 1
@@ -180,15 +186,15 @@ OTHER = [
 ]
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("storage,streaming", [("f32", "aa"), ("bf16", "aa"), ("f32", "pull"), ("bf16", "pull")])
 @pytest.mark.parametrize("D,Q,doms", OTHER, ids=["D3Q39", "D2Q33"])
-def test_other_lattices_batch_equals_single(D, Q, doms, storage):
+def test_other_lattices_batch_equals_single(D, Q, doms, storage, streaming):
     """D3Q39 and D2Q33 domains in the batch: every mode bitwise equals
     single-domain runs of the same domains."""
     nsteps = 5
     res = {}
     for mode in (esb.PER_DOMAIN, esb.PER_STEP, esb.PERSISTENT):
-        b = esb.Batch(D, Q, doms, storage=storage)
+        b = esb.Batch(D, Q, doms, storage=storage, streaming=streaming)
         for k, d in enumerate(doms):
             b.init_fields(k, *workloads.random_state(d["dims"], seed=200 + k))
         b.step(nsteps, mode=mode)
@@ -205,13 +211,14 @@ def test_other_lattices_batch_equals_single(D, Q, doms, storage):
                 assert np.array_equal(g, p[k][1]), (mode, k)
 
 
-def test_benchmark_batch_equals_single_domains():
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+def test_benchmark_batch_equals_single_domains(streaming):
     """The benchmark's 256-domain batch (21.8M cells), autotuned, three
     persistent steps: the smallest and largest domains and one of each N_f
     equal single-domain runs of the same domains bitwise."""
     doms = workloads.batch_domains(256)
     descs = [dict(dims=(d["nx"], d["ny"]), Nf=d["Nf"], Pr=d["Pr"], tau=d["tau"]) for d in doms]
-    bt = esb.Batch(2, 37, descs)
+    bt = esb.Batch(2, 37, descs, streaming=streaming)
     for k, d in enumerate(doms):
         bt.init_fields(k, *workloads.batch_fields(d))
     bt.autotune()
@@ -233,3 +240,47 @@ def test_benchmark_batch_equals_single_domains():
             assert np.array_equal(g, gb), k
     del bt
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+@pytest.mark.parametrize("mode", [esb.PERSISTENT, esb.PER_STEP, esb.PER_DOMAIN])
+def test_calls_starting_at_odd_step_counts(mode, streaming):
+    """Calls of 1, 2 and 3 steps (the second and third start at an odd step
+    count): populations and moments equal single-domain runs bitwise after
+    each call, and the FP64 totals agree."""
+    b = make_batch(streaming=streaming)
+    lats = []
+    for k, d in enumerate(DOMS):
+        lat = esb.Lattice(2, 37, d["Nf"], d["Pr"], d["tau"], d["dims"], kappa=d.get("kappa", 0.2))
+        lat.init_fields(*fields_of(k, d))
+        lats.append(lat)
+    for n in (1, 2, 3):
+        b.step(n, mode=mode)
+        assert b.status() == 0
+        for k, lat in enumerate(lats):
+            lat.step(n)
+            f, g = lat.read_populations()
+            fb, gb = b.read_populations(k)
+            assert np.array_equal(f, fb), (n, k)
+            if g is not None:
+                assert np.array_equal(g, gb), (n, k)
+            ml, mb = lat.read_moments(), b.read_moments(k)
+            for key in ml:
+                assert np.array_equal(ml[key], mb[key]), (n, k, key)
+            assert np.allclose(lat.totals(), b.totals(k), rtol=1e-12, atol=1e-12 * np.prod(DOMS[k]["dims"]))
+
+
+def test_two_batches_stepping_at_once():
+    """Persistent launches of two batches issued back to back on their own
+    streams, with no host synchronisation in between: the library orders
+    them, so neither barrier wait times out, and the A-A and two-copy
+    batches stay bitwise equal after every call (odd and even starts)."""
+    a = make_batch()
+    p = make_batch(streaming="pull")
+    for n in (1, 2, 3, 4):
+        a.step(n, mode=esb.PERSISTENT)
+        p.step(n, mode=esb.PERSISTENT)
+        a.step(n, mode=esb.PERSISTENT)
+        p.step(n, mode=esb.PERSISTENT)
+        assert a.status() == 0 and p.status() == 0
+        assert same(pops(a), pops(p)), n
