@@ -63,24 +63,46 @@ def bytes_per_cell(Q, npop, storage):
     return 2 * Q * npop * (4 if storage == "f32" else 2)
 
 
+PAD_CANDIDATES = (0, 16384, 24576, 49152)   # plane padding, bytes
+
+
 def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, warmup, tune_cache, streaming="pull"):
+    """Autotune the launch shape, pick the plane padding (the candidate
+    layout with the highest rate over a short run, keeping the allocation
+    that was measured), then time `steps` steps after `warmup` from the
+    initial state."""
     log(f"D{D}Q{Q} {dims} {storage} {streaming}: init")
-    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, streaming=streaming)
+    ncell = int(np.prod(dims))
+    best, tile, pad_rates = None, None, {}
+    for pad in PAD_CANDIDATES:
+        lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, streaming=streaming, plane_pad=pad)
+        lat.init_fields(*fields)
+        if tile is None:
+            tile = lat.autotune(cache_path=tune_cache)
+        else:
+            lat.set_tile(*tile[0], parity=0)
+            lat.set_tile(*tile[1], parity=1)
+        lat.step(4)
+        ms, _ = lat.step_timed(40)
+        pad_rates[pad] = round(ncell * 40 / (ms * 1e-3) / 1e6, 1)
+        if best is None or pad_rates[pad] > pad_rates[best[0]]:
+            best = (pad, lat)
+        del lat
+        torch.cuda.empty_cache()
+    pad, lat = best
     lat.init_fields(*fields)
-    tile = lat.autotune(cache_path=tune_cache)
-    log(f"D{D}Q{Q} {dims} {storage} {streaming}: tile {tile}, timing {steps} steps")
+    log(f"D{D}Q{Q} {dims} {storage} {streaming}: tile {tile}, plane pad {pad} ({pad_rates}), timing {steps} steps")
     lat.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     total_ms, per = lat.step_timed(steps)       # HIP events around every launch, on the lattice's stream
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ncell = int(np.prod(dims))
     # after `warmup` steps the first timed launch has parity warmup % 2
     first_odd = warmup % 2 == 1
     odd = per[0::2] if first_odd else per[1::2]
     even = per[1::2] if first_odd else per[0::2]
-    return dict(lat=lat, tile=tile, total_ms=total_ms, wall_s=wall, ncell=ncell,
+    return dict(lat=lat, tile=tile, plane_pad=pad, pad_rates=pad_rates, total_ms=total_ms, wall_s=wall, ncell=ncell,
                 mlups=ncell * steps / (total_ms * 1e-3) / 1e6, odd_ms=float(np.mean(odd)),
                 even_ms=float(np.mean(even)), launch_ms=float(np.mean(per)))
 
@@ -308,6 +330,8 @@ def main():
                    "streaming": "two-copy pull (reads x - c_i, aligned writes; bitwise equal to A-A in place)",
                    "tile": {p: dict(zip(("block", "order", "policy", "cells_per_item"), t))
                             for p, t in zip(("even_step", "odd_step"), main_run["tile"])},
+                   "plane_pad": main_run["plane_pad"],
+                   "plane_pad_MLUPS_40_steps": main_run["pad_rates"],
                    "algorithmic_bytes_per_cell_step": bytes_per_cell(Q, 2, "f32"),
                    "hbm_GBs_per_step_avg": round(bpl / (step_ms * 1e-3) / 1e9, 1)},
         "roofline": roof,
@@ -327,7 +351,8 @@ def main():
             "odd_kernel": {"avg_launch_ms": round(r["odd_ms"], 4),
                            "frac_of_hbm_peak": round(bpl / (r["odd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                            "traffic": measured_traffic("aa_odd", r["tile"][1])},
-            "tile": r["tile"]}
+            "tile": r["tile"], "plane_pad": r["plane_pad"],
+            "plane_pad_MLUPS_40_steps": r["pad_rates"]}
         del r
         torch.cuda.empty_cache()
     if "pr" in variants:
@@ -338,7 +363,8 @@ def main():
                             tune_cache)
             var[f"d2q37_4096_f32_pr{pr:g}"] = {"mlups": round(r["mlups"], 1),
                                                "roofline_frac": round(bpl / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                               "streaming": "pull", "tile": r["tile"]}
+                                               "streaming": "pull", "tile": r["tile"], "plane_pad": r["plane_pad"],
+            "plane_pad_MLUPS_40_steps": r["pad_rates"]}
             del r
             torch.cuda.empty_cache()
     for storage in ("f16", "bf16"):
@@ -349,7 +375,8 @@ def main():
         var[f"d2q37_4096_{storage}_dev"] = {"mlups": round(r["mlups"], 1), "ms_per_step": round(r["total_ms"] / args.steps, 4),
                                             "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                             "GBs_per_step": round(b / (r["total_ms"] / args.steps * 1e-3) / 1e9, 1),
-                                            "streaming": "pull", "tile": r["tile"]}
+                                            "streaming": "pull", "tile": r["tile"], "plane_pad": r["plane_pad"],
+            "plane_pad_MLUPS_40_steps": r["pad_rates"]}
         del r
         torch.cuda.empty_cache()
     del fields
@@ -364,7 +391,8 @@ def main():
                                     "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                                     "GBs_per_step": round(b / (r["total_ms"] / s3 * 1e-3) / 1e9, 1),
                                     "traffic": pull_traffic(r["tile"], "D3Q39"),
-                                    "streaming": "pull", "tile": r["tile"]}
+                                    "streaming": "pull", "tile": r["tile"], "plane_pad": r["plane_pad"],
+            "plane_pad_MLUPS_40_steps": r["pad_rates"]}
         del r
         torch.cuda.empty_cache()
         # the same vortex with BF16 deviation storage (f and g paired)
@@ -372,7 +400,8 @@ def main():
         b = bytes_per_cell(39, 2, "bf16") * n3 ** 3
         var["d3q39_256cube_bf16"] = {"mlups": round(r["mlups"], 1),
                                      "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                     "streaming": "pull", "tile": r["tile"]}
+                                     "streaming": "pull", "tile": r["tile"], "plane_pad": r["plane_pad"],
+            "plane_pad_MLUPS_40_steps": r["pad_rates"]}
         del r, f3
         torch.cuda.empty_cache()
     if "d2q33" in variants:
@@ -384,7 +413,8 @@ def main():
         b = bytes_per_cell(33, 2, "f32") * n2 * n2
         var["d2q33_4096_f32"] = {"mlups": round(r["mlups"], 1),
                                  "roofline_frac": round(b / (r["launch_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                 "streaming": "pull", "tile": r["tile"]}
+                                 "streaming": "pull", "tile": r["tile"], "plane_pad": r["plane_pad"],
+            "plane_pad_MLUPS_40_steps": r["pad_rates"]}
         del r, f2
         torch.cuda.empty_cache()
     if "batch" in variants:

@@ -42,7 +42,8 @@
  *     rest-state value; ESBGK_F16_DEV and ESBGK_BF16_DEV keep it as an FP16 or
  *     BF16 deviation multiplied by a per-direction power of two near 1/w_i.
  *     Collision arithmetic is FP32 in all modes.  ESBGK_PULL or-ed into the
- *     storage argument selects the two-copy streaming scheme.  One direction
+ *     storage argument selects the two-copy streaming scheme, and
+ *     ESBGK_PLANE_PAD(n) a padding after every plane.  One direction
  *     of all cells forms a plane; the Q planes of a population form a set of
  *     at most 4 GiB (the largest domain: 2^32 / (Q * 4) cells for FP32, and
  *     for FP16/BF16 with N_f > 0, whose f_i and g_i share one 4-byte element;
@@ -78,8 +79,7 @@ extern "C" {
 #define ESBGK_F16_DEV 1
 #define ESBGK_BF16_DEV 2
 
-/* Streaming scheme, or-ed into a storage argument (single-domain handles).
- * Without it the populations are one copy updated in place with the A-A
+/* Streaming scheme, or-ed into a storage argument.  Without it the populations are one copy updated in place with the A-A
  * pattern: even steps read and write each cell's own slots (writing f_i
  * into slot opp(i)), odd steps read slot opp(i) at x - c_i and write slot i
  * at x + c_i.  With ESBGK_PULL the library keeps two copies: every step
@@ -88,6 +88,17 @@ extern "C" {
  * the storage; the arithmetic and the results are bit for bit those of
  * A-A. */
 #define ESBGK_PULL 0x10
+
+/* Plane padding, or-ed into a storage argument: n (0..255) times 4 KiB of
+ * unused bytes after every plane, which changes the distance between the
+ * address streams of the Q (or 2Q) planes a step reads and writes at once.
+ * The HBM rate of those streams depends on that distance: on MI355X a 4096^2
+ * D2Q37 FP32 domain (planes exactly 64 MiB apart) moves 5.46 TB/s unpadded
+ * and 5.56-5.60 TB/s with n = 4, and some distances cost a quarter of the
+ * rate (a 4096 x 4064 domain unpadded: 3.9-4.1 TB/s).  Results do not
+ * depend on it; checkpoints are written unpadded and load into any
+ * padding. */
+#define ESBGK_PLANE_PAD(n) (((n) & 0xff) << 8)
 
 typedef struct esbgk_lattice esbgk_t;
 typedef struct esbgk_batch esbgk_batch_t;
@@ -214,9 +225,10 @@ int esbgk_read_populations(esbgk_t *h, double *f, double *g);
 int esbgk_write_populations(esbgk_t *h, const double *f, const double *g);
 
 /* Checkpoint the raw state (storage, parameters, step counter) to a file /
- * restore it into a handle created with the same lattice, dims, N_f and
- * storage.  Synchronous.  ESBGK_EIO on file errors, ESBGK_EINVAL on a
- * mismatching handle. */
+ * restore it into a handle created with the same lattice, dims, N_f,
+ * storage mode and streaming scheme (any plane padding: the file holds the
+ * unpadded layout).  Synchronous.  ESBGK_EIO on file errors, ESBGK_EINVAL on
+ * a mismatching handle. */
 int esbgk_save(esbgk_t *h, const char *path);
 int esbgk_load(esbgk_t *h, const char *path);
 
@@ -252,8 +264,9 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
  * reps timed launches on the default stream, 256 <= cells <= 2.8e7).
  * *gbps counts read plus written bytes and is the best of three placements
  * (in place on each of two buffers, and a copy from one to the other), four
- * occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU) and two store
- * cache policies (default and non-temporal).
+ * occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU), two store
+ * cache policies (default and non-temporal) and two plane strides
+ * (unpadded, and 16 KiB of padding per plane).
  * Allocates and frees its own buffers (four sets of 37 planes).  A roofline
  * reference next to the published HBM peak, not part of the scheme. */
 int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps);

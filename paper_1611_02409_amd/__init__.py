@@ -35,12 +35,16 @@ PULL = 0x10   # two-copy pull streaming (or-ed into the storage code)
 STREAMING = {"aa": 0, "pull": PULL}
 
 
-def _storage_code(storage: str, streaming: str = "aa") -> int:
+def _storage_code(storage: str, streaming: str = "aa", plane_pad: int = 0) -> int:
+    """Storage argument of the C ABI; plane_pad is the padding after every
+    plane in bytes (a multiple of 4096, at most 255 * 4096)."""
     if storage not in STORAGE:
         raise ValueError(f"storage must be one of {sorted(STORAGE)}")
     if streaming not in STREAMING:
         raise ValueError(f"streaming must be one of {sorted(STREAMING)}")
-    return STORAGE[storage] | STREAMING[streaming]
+    if plane_pad % 4096 or not 0 <= plane_pad <= 255 * 4096:
+        raise ValueError("plane_pad must be a multiple of 4096 bytes in [0, 255 * 4096]")
+    return STORAGE[storage] | STREAMING[streaming] | ((plane_pad // 4096) << 8)
 
 
 ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EDEVICE", -5: "ESTATE", -6: "ENONFINITE", -7: "EIO"}
@@ -142,30 +146,34 @@ def _dims(dims):
     return (ctypes.c_int64 * 3)(*(list(dims) + [1] * (3 - len(dims))))
 
 
-def storage_bytes(D, Q, Nf, dims, storage="f32", streaming="aa") -> int:
+def storage_bytes(D, Q, Nf, dims, storage="f32", streaming="aa", plane_pad=0) -> int:
     out = ctypes.c_size_t()
-    _check(_lib.esbgk_storage_bytes(D, Q, Nf, _dims(dims), _storage_code(storage, streaming), ctypes.byref(out)))
+    _check(_lib.esbgk_storage_bytes(D, Q, Nf, _dims(dims), _storage_code(storage, streaming, plane_pad),
+                                    ctypes.byref(out)))
     return out.value
 
 
 class Lattice:
     """One periodic domain.  Fields use numpy shape (ny, nx) / (nz, ny, nx),
     velocity (D, ...).  streaming: "aa" (one copy, A-A in place) or "pull"
-    (two copies, aligned stores; same results bit for bit)."""
+    (two copies, aligned stores; same results bit for bit).  plane_pad:
+    unused bytes after every plane (a multiple of 4096), which moves the
+    planes' address streams apart; results do not depend on it."""
 
     def __init__(self, D: int, Q: int, Nf: int, Pr: float, tau: float, dims, storage: str = "f32",
-                 kappa: float = 0.2, device: int = 0, stream=None, streaming: str = "aa"):
+                 kappa: float = 0.2, device: int = 0, stream=None, streaming: str = "aa", plane_pad: int = 0):
         self.D, self.Q, self.Nf, self.Pr, self.tau = D, Q, Nf, Pr, tau
         self.dims = tuple(int(d) for d in dims)
         if len(self.dims) != D:
             raise ValueError("dims must have D entries")
         self.storage = storage
         self.streaming = streaming
-        code = _storage_code(storage, streaming)
+        code = _storage_code(storage, streaming, plane_pad)
+        self.plane_pad = plane_pad
         self.ncell = int(np.prod(self.dims))
         self.shape = tuple(reversed(self.dims))
         self._h = None
-        nbytes = storage_bytes(D, Q, Nf, self.dims, storage, streaming)
+        nbytes = storage_bytes(D, Q, Nf, self.dims, storage, streaming, plane_pad)
         self.device = torch.device("cuda", device)
         self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -331,7 +339,7 @@ class Batch:
     together.  `domains` is a list of dicts with keys dims, Nf, Pr, tau and
     optionally kappa; streaming "aa" (in place) or "pull" (two copies)."""
 
-    def __init__(self, D: int, Q: int, domains, storage: str = "f32", streaming: str = "aa"):
+    def __init__(self, D: int, Q: int, domains, storage: str = "f32", streaming: str = "aa", plane_pad: int = 0):
         self.D, self.Q, self.storage, self.streaming = D, Q, storage, streaming
         self.domains = [dict(d) for d in domains]
         arr = (DomainDesc * len(domains))()
@@ -341,7 +349,8 @@ class Batch:
                                 (ctypes.c_int64 * 3)(*dims))
         h = _vp()
         self._h = None
-        _check(_lib.esbgk_batch_create(D, Q, len(domains), arr, _storage_code(storage, streaming), ctypes.byref(h)))
+        _check(_lib.esbgk_batch_create(D, Q, len(domains), arr, _storage_code(storage, streaming, plane_pad),
+                                       ctypes.byref(h)))
         self._h = h
 
     def __del__(self, _destroy=_lib.esbgk_batch_destroy):

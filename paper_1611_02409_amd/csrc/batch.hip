@@ -243,11 +243,7 @@ int esbgk_batch_create(int D, int Q, int n, const esbgk_domain_desc *desc, int s
         return ESBGK_EINVAL;
     }
     *out = nullptr;
-    const int codec = storage & ~ESBGK_PULL;
-    if (codec < 0 || codec > 2) {
-        set_error("unknown storage mode %d", storage);
-        return ESBGK_EINVAL;
-    }
+    const int codec = storage_codec(storage);
     auto *b = new (std::nothrow) esbgk_batch();
     if (!b) {
         set_error("host allocation failed");

@@ -86,8 +86,8 @@ int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, cons
         set_error("dims is NULL");
         return ESBGK_EINVAL;
     }
-    const int codec = storage & ~ESBGK_PULL;
-    if (codec < 0 || codec > 2) {
+    const int codec = storage_codec(storage);
+    if (storage < 0 || (storage & ~(3 | ESBGK_PULL | ESBGK_PLANE_PAD(0xff))) || codec > 2) {
         set_error("unknown storage mode %d", storage);
         return ESBGK_EINVAL;
     }
@@ -120,30 +120,55 @@ int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, cons
     out.esize = codec == ESBGK_F32 ? 4 : 2;
     out.npop = Nf > 0 ? 2 : 1;
     out.paired = codec != ESBGK_F32 && out.npop == 2;
-    const uint64_t ebytes = out.esize * (out.paired ? 2 : 1);
-    out.plane_bytes = ncell * ebytes;
-    const uint64_t set_bytes = out.plane_bytes * (uint64_t)Q;
+    out.geom.ncell = (uint32_t)ncell;
+    if (int rc2 = set_layout(out, storage_plane_pad(storage))) return rc2;
+    out.coll = make_coll(out.lc, out.prm, D, Nf, kappa);
+    Geom &g = out.geom;
+    g.nx = (uint32_t)nd[0];
+    g.ny = (uint32_t)nd[1];
+    g.nz = (uint32_t)nd[2];
+    g.by_nx = make_fastdiv(g.nx);
+    g.by_nxy = make_fastdiv(g.nx * g.ny);
+    return ESBGK_OK;
+}
+
+int set_layout(DomainSetup &su, uint64_t plane_pad) {
+    const uint64_t ncell = su.geom.ncell;
+    const int Q = su.lc.Q;
+    const uint64_t ebytes = su.esize * (su.paired ? 2 : 1);
+    if (plane_pad & 255) {
+        set_error("plane padding must be a multiple of 256 bytes");
+        return ESBGK_EINVAL;
+    }
+    const uint64_t plane = ncell * ebytes + plane_pad;
+    const uint64_t set_bytes = plane * (uint64_t)Q;
     if (set_bytes >= ((uint64_t)1 << 32)) {
         set_error("one population set would take %llu bytes; the limit is 4 GiB per set (%llu cells for this "
                   "lattice, storage and N_f)",
                   (unsigned long long)set_bytes, (unsigned long long)((((uint64_t)1 << 32) - 1) / (ebytes * Q)));
         return ESBGK_EUNSUPPORTED;
     }
+    su.plane_pad = plane_pad;
+    su.plane_bytes = plane;
     // planes are 256-byte aligned inside a set only through the cell count;
     // sets and copies start 256-byte aligned
-    out.set_stride = (set_bytes + 255) & ~uint64_t(255);
-    const int nsets = out.paired ? 1 : out.npop;
-    out.g_off = out.npop == 2 ? (out.paired ? out.esize : out.set_stride) : 0;
-    out.copy_bytes = out.set_stride * nsets;
-    out.bytes = out.copy_bytes * out.copies;
-    out.coll = make_coll(out.lc, out.prm, D, Nf, kappa);
-    Geom &g = out.geom;
-    g.nx = (uint32_t)nd[0];
-    g.ny = (uint32_t)nd[1];
-    g.nz = (uint32_t)nd[2];
-    g.ncell = (uint32_t)ncell;
-    g.by_nx = make_fastdiv(g.nx);
-    g.by_nxy = make_fastdiv(g.nx * g.ny);
+    su.set_stride = (set_bytes + 255) & ~uint64_t(255);
+    const int nsets = su.paired ? 1 : su.npop;
+    su.g_off = su.npop == 2 ? (su.paired ? su.esize : su.set_stride) : 0;
+    su.copy_bytes = su.set_stride * nsets;
+    su.bytes = su.copy_bytes * su.copies;
+    return ESBGK_OK;
+}
+
+int copy_layout(char *dst, const DomainSetup &dl, const char *src, const DomainSetup &sl, int copies,
+                hipMemcpyKind kind, hipStream_t s) {
+    const uint64_t width = (uint64_t)dl.geom.ncell * dl.esize * (dl.paired ? 2 : 1);
+    const int nsets = dl.paired ? 1 : dl.npop;
+    for (int c = 0; c < copies; c++)
+        for (int k = 0; k < nsets; k++)
+            ESBGK_HIP(hipMemcpy2DAsync(dst + c * dl.copy_bytes + k * dl.set_stride, dl.plane_bytes,
+                                       src + c * sl.copy_bytes + k * sl.set_stride, sl.plane_bytes, width, dl.lc.Q,
+                                       kind, s));
     return ESBGK_OK;
 }
 
@@ -801,10 +826,12 @@ int esbgk_save(esbgk_t *h, const char *path) {
         set_error("path is NULL");
         return ESBGK_EINVAL;
     }
+    // the current state only (one copy), in the unpadded layout
+    DomainSetup su0 = h->su;
+    if (int rc = set_layout(su0, 0)) return rc;
     std::vector<char> host;
-    if (int rc = host_buffer(host, h->su.copy_bytes)) return rc;
-    // the current state only (one copy)
-    ESBGK_HIP(hipMemcpyAsync(host.data(), h->fb(), h->su.copy_bytes, hipMemcpyDeviceToHost, h->stream));
+    if (int rc = host_buffer(host, su0.copy_bytes)) return rc;
+    if (int rc = copy_layout(host.data(), su0, h->fb(), h->su, 1, hipMemcpyDeviceToHost, h->stream)) return rc;
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     CkptHeader hd{};
     std::memcpy(hd.magic, "ESBGKCK2", 8);
@@ -812,14 +839,14 @@ int esbgk_save(esbgk_t *h, const char *path) {
     hd.D = h->D;
     hd.Q = h->Q;
     hd.Nf = h->Nf;
-    hd.storage = h->storage;
+    hd.storage = storage_unpadded(h->storage);
     for (int d = 0; d < 3; d++) hd.dims[d] = h->dims[d];
     hd.steps = h->steps;
     hd.flags = h->from_step ? 1 : 0;
     hd.Pr = h->Pr;
     hd.tau = h->tau;
     hd.kappa = h->kappa;
-    hd.bytes = h->su.copy_bytes;
+    hd.bytes = su0.copy_bytes;
     FILE *fp = std::fopen(path, "wb");
     if (!fp) {
         set_error("cannot open %s for writing", path);
@@ -852,8 +879,13 @@ int esbgk_load(esbgk_t *h, const char *path) {
         set_error("%s is not an esbgk checkpoint", path);
         return ESBGK_EIO;
     }
-    bool same = hd.D == h->D && hd.Q == h->Q && hd.Nf == h->Nf && hd.storage == h->storage &&
-                hd.bytes == h->su.copy_bytes;
+    DomainSetup su0 = h->su;   // the unpadded layout checkpoints are written in
+    if (int rc = set_layout(su0, 0)) {
+        std::fclose(fp);
+        return rc;
+    }
+    bool same = hd.D == h->D && hd.Q == h->Q && hd.Nf == h->Nf && hd.storage == storage_unpadded(h->storage) &&
+                hd.bytes == su0.copy_bytes;
     for (int d = 0; d < 3; d++) same = same && hd.dims[d] == h->dims[d];
     if (!same) {
         std::fclose(fp);
@@ -890,7 +922,7 @@ int esbgk_load(esbgk_t *h, const char *path) {
     h->su.coll = make_coll(h->su.lc, prm, h->D, h->Nf, hd.kappa);
     h->steps = hd.steps;
     h->from_step = (hd.flags & 1) != 0;
-    ESBGK_HIP(hipMemcpyAsync(h->fb(), host.data(), host.size(), hipMemcpyHostToDevice, h->stream));
+    if (int rc = copy_layout(h->fb(), h->su, host.data(), su0, 1, hipMemcpyHostToDevice, h->stream)) return rc;
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->initialized = true;
     return ESBGK_OK;

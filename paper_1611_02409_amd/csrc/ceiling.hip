@@ -14,12 +14,13 @@ namespace {
 // share a CU (the pattern streams best at a few waves per SIMD); touch is 0.
 // SCP: cache-policy bits of the stores (0 default, 2 non-temporal).
 template <int NP, int SCP>
-__global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_t ncell, uint32_t set_bytes, int touch) {
+__global__ __launch_bounds__(256) void k_stream_rw(char *src, char *dst, uint32_t ncell, uint32_t plane_bytes,
+                                                   uint32_t set_bytes, int touch) {
     extern __shared__ float occupancy_lds[];
     const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
-    const Sets R(src, src + set_bytes, ncell * 4u, set_bytes);
-    const Sets W(dst, dst + set_bytes, ncell * 4u, set_bytes);
+    const Sets R(src, src + set_bytes, plane_bytes, set_bytes);
+    const Sets W(dst, dst + set_bytes, plane_bytes, set_bytes);
     float v[NP];
 #pragma unroll
     for (int i = 0; i < NP; i++) v[i] = ld<ST_F32>(i < NP / 2 ? R.f : R.g, c * 4u, R.so(i % (NP / 2)));
@@ -39,8 +40,9 @@ using namespace esbgk;
 // Best of three placements of the pattern (in place on each of two buffers
 // allocated one after the other, and a copy from one to the other: where a
 // buffer lands in HBM moves such streams by a few per cent), of four
-// occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU) and of two
-// store policies (default and non-temporal, the two the step kernels use).
+// occupancies (1, 2, 3 and up to 8 work-groups of 256 per CU), of two
+// store policies (default and non-temporal, the two the step kernels use)
+// and of two plane strides (unpadded, and 16 KiB of padding per plane).
 extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     clear_error();
     if (cells < 256 || cells > (int64_t)14000000 * 2 || reps < 1 || !gbps) {
@@ -48,12 +50,13 @@ extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
         return ESBGK_EINVAL;
     }
     const uint32_t n = (uint32_t)cells;
-    const uint32_t set_bytes = 37u * n * 4u;
+    const uint32_t data_bytes = 37u * n * 4u;             // one set's values
+    const uint32_t alloc_set = 37u * (n * 4u + 16384u);   // room for the padded layout
     char *p[2] = {nullptr, nullptr};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = ESBGK_OK;
     for (int k = 0; k < 2 && rc == ESBGK_OK; k++) {
-        if (hipMalloc(&p[k], 2ull * set_bytes) != hipSuccess || hipMemset(p[k], 0, 2ull * set_bytes) != hipSuccess) {
+        if (hipMalloc(&p[k], 2ull * alloc_set) != hipSuccess || hipMemset(p[k], 0, 2ull * alloc_set) != hipSuccess) {
             set_error("allocation of the stream buffers failed");
             rc = ESBGK_ENOMEM;
         }
@@ -67,22 +70,27 @@ extern "C" int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps) {
     // LDS per CU is 160 KiB: a work-group asking for a bit over 160/(k+1) KiB
     // leaves room for at most k of them
     const size_t lds_for[4] = {96 * 1024, 60 * 1024, 44 * 1024, 0};
-    for (int pass = 0; pass < 3 && rc == ESBGK_OK; pass++) {
-        char *src = p[pass == 1 ? 1 : 0], *dst = p[pass == 0 ? 0 : 1];
-        for (int pol = 0; pol < 2 && rc == ESBGK_OK; pol++) for (size_t lds : lds_for) {
-            auto kern = pol ? k_stream_rw<74, 2> : k_stream_rw<74, 0>;
-            for (int w = 0; w < 2; w++) kern<<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
-            (void)hipEventRecord(e0, nullptr);
-            for (int r = 0; r < reps; r++) kern<<<nb, 256, lds>>>(src, dst, n, set_bytes, 0);
-            (void)hipEventRecord(e1, nullptr);
-            if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                set_error("stream kernel failed");
-                rc = ESBGK_EDEVICE;
-                break;
+    for (uint32_t pad : {0u, 16384u}) {
+        const uint32_t plane = n * 4u + pad, set_bytes = 37u * plane;
+        for (int pass = 0; pass < 3 && rc == ESBGK_OK; pass++) {
+            char *src = p[pass == 1 ? 1 : 0], *dst = p[pass == 0 ? 0 : 1];
+            for (int pol = 0; pol < 2 && rc == ESBGK_OK; pol++) {
+                for (size_t lds : lds_for) {
+                    auto kern = pol ? k_stream_rw<74, 2> : k_stream_rw<74, 0>;
+                    for (int w = 0; w < 2; w++) kern<<<nb, 256, lds>>>(src, dst, n, plane, set_bytes, 0);
+                    (void)hipEventRecord(e0, nullptr);
+                    for (int r = 0; r < reps; r++) kern<<<nb, 256, lds>>>(src, dst, n, plane, set_bytes, 0);
+                    (void)hipEventRecord(e1, nullptr);
+                    if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        set_error("stream kernel failed");
+                        rc = ESBGK_EDEVICE;
+                        break;
+                    }
+                    float ms = 0;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    best = std::max(best, 2.0 * 2.0 * data_bytes * reps / (ms * 1e-3) / 1e9);
+                }
             }
-            float ms = 0;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            best = std::max(best, 2.0 * 2.0 * set_bytes * reps / (ms * 1e-3) / 1e9);
         }
     }
     if (rc == ESBGK_OK) *gbps = best;

@@ -44,6 +44,12 @@ int host_buffer(std::vector<T> &v, uint64_t n) {
 
 FastDiv make_fastdiv(uint32_t d);
 
+// Parts of a storage argument: the codec (ESBGK_F32, ESBGK_F16_DEV or
+// ESBGK_BF16_DEV) and the plane padding in bytes.
+inline int storage_codec(int storage) { return storage & 3; }
+inline uint64_t storage_plane_pad(int storage) { return (uint64_t)((storage >> 8) & 0xff) * 4096u; }
+inline int storage_unpadded(int storage) { return storage & ~ESBGK_PLANE_PAD(0xff); }
+
 // Validate (D, Q, N_f, Pr, tau, kappa, dims, storage) and fill the derived
 // constants.  Returns ESBGK_OK or an error code with the message set.
 struct DomainSetup {
@@ -56,7 +62,9 @@ struct DomainSetup {
     int copies;      // 1: A-A in place; 2: two-copy pull
     uint32_t esize;        // bytes per stored value
     bool paired;           // f_i and g_i side by side in one element (FP16/BF16 storage, N_f > 0)
-    uint64_t plane_bytes;  // one direction's values of all cells (both populations when paired)
+    uint64_t plane_bytes;  // bytes from one direction's plane to the next: the values of all
+                           // cells (both populations when paired) plus plane_pad
+    uint64_t plane_pad;    // padding after each plane (a multiple of 256; 0 unless chosen)
     uint64_t set_stride;   // bytes of a population set (256-byte aligned)
     uint64_t g_off;        // bytes from f to g: the next set, or 2 within a paired element
     uint64_t copy_bytes;   // bytes of one copy of the state
@@ -65,6 +73,16 @@ struct DomainSetup {
 
 int setup_domain(int D, int Q, int Nf, double Pr, double tau, double kappa, const int64_t *dims, int storage,
                  DomainSetup &out);
+
+// Recompute the storage sizes of a set-up domain for another plane padding
+// (bytes, a multiple of 256).  ESBGK_EUNSUPPORTED if a set would exceed 4 GiB.
+int set_layout(DomainSetup &su, uint64_t plane_pad);
+
+// Enqueue a copy of the population storage from one layout of a domain to
+// another (same domain, planes padded differently): `copies` copies of the
+// state, every set and plane.  Plane padding is not copied.
+int copy_layout(char *dst, const DomainSetup &dl, const char *src, const DomainSetup &sl, int copies,
+                hipMemcpyKind kind, hipStream_t s);
 
 // Collision constants for the given parameters.
 Coll make_coll(const LatticeConsts &lc, const double prm[4], int D, int Nf, double kappa);

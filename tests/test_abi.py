@@ -102,6 +102,25 @@ def test_storage_bytes(esb):
     assert esb.storage_bytes(2, 37, 0, (33, 35), "bf16", "pull") == 2 * ((37 * 33 * 35 * 2 + 255) // 256 * 256)
     with pytest.raises(ValueError):
         esb.storage_bytes(2, 37, 3, (64, 64), "f32", "push")
+    # plane padding: unused bytes after every plane
+    pad = 3 * 4096
+    assert esb.storage_bytes(2, 37, 3, (4096, 4096), "f32", plane_pad=pad) == 2 * 37 * (4096 * 4096 * 4 + pad)
+    assert esb.storage_bytes(2, 37, 1, (33, 35), "f16", "pull", plane_pad=pad) == \
+        2 * ((37 * (33 * 35 * 4 + pad) + 255) // 256 * 256)
+    for bad in (100, 256 * 4096, -4096):
+        with pytest.raises(ValueError):
+            esb.storage_bytes(2, 37, 3, (64, 64), "f32", plane_pad=bad)
+
+
+def test_storage_codes_outside_the_defined_bits_are_rejected(esb):
+    lib = esb._lib
+    out = ctypes.c_size_t()
+    dims = (ctypes.c_int64 * 3)(64, 64, 1)
+    for code in (3, 4, 0x20, 0x10000, -1):
+        assert lib.esbgk_storage_bytes(2, 37, 3, dims, code, ctypes.byref(out)) == -1, code
+        assert "storage" in lib.esbgk_last_error().decode()
+    assert lib.esbgk_storage_bytes(2, 37, 3, dims, esb.PULL | (255 << 8), ctypes.byref(out)) == 0
+    assert out.value == 2 * 2 * 37 * (64 * 64 * 4 + 255 * 4096)
 
 
 def test_batch_create_validates_before_touching_a_device(esb):
