@@ -96,7 +96,9 @@ _sig("esbgk_stream_ceiling", [ctypes.c_int64, ctypes.c_int, _dp])
 
 
 def stream_ceiling(cells: int = 4096 * 4096, reps: int = 10) -> float:
-    """GB/s of an arithmetic-free in-place read+write of 74 FP32 planes."""
+    """GB/s (read plus written) of an arithmetic-free read and write of 74
+    FP32 planes of `cells` cells: the best over buffer placements,
+    occupancies, store cache policies and plane strides."""
     out = ctypes.c_double()
     _check(_lib.esbgk_stream_ceiling(int(cells), int(reps), ctypes.byref(out)))
     return out.value

@@ -148,3 +148,11 @@ def test_null_handles_are_rejected(esb):
     assert lib.esbgk_set_walls(None, None, None) == -1
     lib.esbgk_destroy(None)
     lib.esbgk_batch_destroy(None)
+
+
+def test_stream_ceiling_rejects_bad_sizes_without_a_device(esb):
+    lib = esb._lib
+    out = ctypes.c_double()
+    for cells, reps in ((100, 1), (1 << 30, 1), (1 << 20, 0)):
+        assert lib.esbgk_stream_ceiling(cells, reps, ctypes.byref(out)) == -1
+    assert lib.esbgk_stream_ceiling(1 << 20, 1, None) == -1
