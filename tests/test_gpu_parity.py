@@ -34,8 +34,9 @@ def perm_to_oracle(D, Q):
     return np.array([oc.index(tuple(c)) for c in li["c"]]), li
 
 
-def gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, storage="f32", kappa=0.2, streaming="aa"):
-    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, kappa=kappa, streaming=streaming)
+def gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, storage="f32", kappa=0.2, streaming="aa", plane_pad=0):
+    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, kappa=kappa, streaming=streaming,
+                      plane_pad=plane_pad)
     lat.init_fields(*fields)
     if steps:
         lat.step(steps)
@@ -158,16 +159,21 @@ def test_decay_case_moments_match_oracle():
     assert er < 1e-5 and eu < 1e-5 and eT < 1e-5
 
 
-@pytest.mark.parametrize("steps0", [2, 3])
-def test_full_size_one_step_sampled(steps0):
-    """4096^2 FP32 (the benchmark configuration): after steps0 steps, one more
-    step of the GPU at 64 sampled cells equals the oracle's collision of the
-    GPU's own pre-step populations at the neighbours x - c_i, streamed."""
+@pytest.mark.parametrize("steps0,streaming,pad", [(2, "aa", 0), (3, "pull", 16384)])
+def test_full_size_one_step_sampled(steps0, streaming, pad):
+    """4096^2 FP32 (the benchmark workload; with two-copy pull, 16 KiB plane
+    padding and the autotuned launch shape it is the benchmark's launch
+    configuration): after steps0 steps, one more step of the GPU at 64
+    sampled cells equals the oracle's collision of the GPU's own pre-step
+    populations at the neighbours x - c_i, streamed."""
     N = 4096
     D, Q, Nf, Pr, tau = 2, 37, 3, 0.71, 0.6
     fields = workloads.waves_noise_2d(N)
     perm, li = perm_to_oracle(D, Q)
-    lat = gpu_run(D, Q, Nf, Pr, tau, (N, N), fields, steps0)
+    lat = gpu_run(D, Q, Nf, Pr, tau, (N, N), fields, 0, streaming=streaming, plane_pad=pad)
+    if streaming == "pull":
+        lat.autotune()
+    lat.step(steps0)
     rng = np.random.default_rng(steps0)
     cells = np.concatenate([rng.integers(0, N * N, 60), [0, N - 1, N * N - 1, N * (N - 1)]])
     nb = neighbourhood((N, N), cells, li["c"])
@@ -185,7 +191,7 @@ def test_full_size_one_step_sampled(steps0):
     want_g = go[np.arange(cells.size)[:, None], np.arange(Q)[None, :], np.arange(Q)[None, :]]
     ef = float(np.max(np.abs(f1 - want_f) / li["w"]))
     eg = float(np.max(np.abs(g1 - want_g) / li["w"])) / Nf
-    print(f"4096^2 sampled step {steps0}->{steps0 + 1}: f {ef:.2e} g {eg:.2e}")
+    print(f"4096^2 {streaming} pad {pad} sampled step {steps0}->{steps0 + 1}: f {ef:.2e} g {eg:.2e}")
     assert ef < 1e-6 and eg < 1e-6
 
 
@@ -410,39 +416,44 @@ def _random_cases(n=14, seed=1611):
             dims = tuple(int(rng.integers(reach, 14)) for _ in range(3))
         out.append((D, Q, Nf, round(Pr, 3), round(tau, 3), round(kappa, 3), dims,
                     str(rng.choice(["aa", "pull"])), int(rng.integers(1, 6))))
-    return out
+    # plane padding drawn from a generator of its own, so that the cases
+    # above stay what they were
+    pads = np.random.default_rng(9).choice([0, 4096, 12288], size=len(out))
+    return [c + (int(p),) for c, p in zip(out, pads)]
 
 
-@pytest.mark.parametrize("D,Q,Nf,Pr,tau,kappa,dims,streaming,steps", _random_cases())
-def test_random_configurations_match_oracle(D, Q, Nf, Pr, tau, kappa, dims, streaming, steps):
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,kappa,dims,streaming,steps,pad", _random_cases())
+def test_random_configurations_match_oracle(D, Q, Nf, Pr, tau, kappa, dims, streaming, steps, pad):
     fields = workloads.random_state(dims, seed=40 + steps)
     perm, li = perm_to_oracle(D, Q)
-    lat = gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, kappa=kappa, streaming=streaming)
+    lat = gpu_run(D, Q, Nf, Pr, tau, dims, fields, steps, kappa=kappa, streaming=streaming, plane_pad=pad)
     sim = oracle_run(D, Q, Nf, Pr, tau, dims, fields, steps, kappa=kappa)
     fg, gg = lat.read_populations()
     fo, go = sim.get_pops()
     e = pop_error(li["w"], fg, fo[perm])
     eg = pop_error(li["w"], gg, go[perm]) / max(1, Nf) if Nf else 0.0
-    print(f"D{D}Q{Q} Nf={Nf} Pr={Pr} tau={tau} kappa={kappa} {dims} {streaming} x {steps}: pop {e:.2e} g {eg:.2e}")
+    print(f"D{D}Q{Q} Nf={Nf} Pr={Pr} tau={tau} kappa={kappa} {dims} {streaming} pad {pad} x {steps}: "
+          f"pop {e:.2e} g {eg:.2e}")
     assert e < 3e-6 and eg < 3e-6
 
 
 # the benchmark's other full-size workloads in the benchmark's launch
-# configuration (two-copy pull, autotuned launch shape): one step at sampled
-# cells against the oracle's collision of the GPU's own pre-step populations
+# configuration (two-copy pull, autotuned launch shape, the plane padding the
+# benchmark picked for them): one step at sampled cells against the oracle's
+# collision of the GPU's own pre-step populations
 BENCH_CASES = [
-    (3, 39, 2, 0.71, 0.7, (256, 256, 256), "f32"),    # thermal Taylor-Green vortex
-    (2, 37, 3, 0.71, 0.6, (4096, 4096), "f16"),
-    (2, 37, 3, 0.71, 0.6, (4096, 4096), "bf16"),
+    (3, 39, 2, 0.71, 0.7, (256, 256, 256), "f32", 16384),    # thermal Taylor-Green vortex
+    (2, 37, 3, 0.71, 0.6, (4096, 4096), "f16", 0),
+    (2, 37, 3, 0.71, 0.6, (4096, 4096), "bf16", 24576),
 ]
 
 
-@pytest.mark.parametrize("D,Q,Nf,Pr,tau,dims,storage", BENCH_CASES)
-def test_benchmark_workloads_sampled(D, Q, Nf, Pr, tau, dims, storage):
+@pytest.mark.parametrize("D,Q,Nf,Pr,tau,dims,storage,pad", BENCH_CASES)
+def test_benchmark_workloads_sampled(D, Q, Nf, Pr, tau, dims, storage, pad):
     n = int(np.prod(dims))
     fields = workloads.taylor_green_3d(dims[0]) if D == 3 else workloads.waves_noise_2d(dims[0])
     perm, li = perm_to_oracle(D, Q)
-    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, streaming="pull")
+    lat = esb.Lattice(D, Q, Nf, Pr, tau, dims, storage=storage, streaming="pull", plane_pad=pad)
     lat.init_fields(*fields)
     lat.autotune()
     lat.step(4)
