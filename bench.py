@@ -69,8 +69,8 @@ PAD_CANDIDATES = (0, 16384, 24576, 49152)   # plane padding, bytes
 def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, warmup, tune_cache, streaming="pull"):
     """Autotune the launch shape, pick the plane padding (the candidate
     layout with the highest rate over a short run, keeping the allocation
-    that was measured), then time `steps` steps after `warmup` from the
-    initial state."""
+    that was measured), tune the launch shape again on it, then time `steps`
+    steps after `warmup` from the initial state."""
     log(f"D{D}Q{Q} {dims} {storage} {streaming}: init")
     ncell = int(np.prod(dims))
     best, tile, pad_rates = None, None, {}
@@ -91,6 +91,8 @@ def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, war
         torch.cuda.empty_cache()
     pad, lat = best
     lat.init_fields(*fields)
+    if pad != PAD_CANDIDATES[0]:
+        tile = lat.autotune(cache_path=tune_cache)     # launch shape again, on the chosen allocation
     log(f"D{D}Q{Q} {dims} {storage} {streaming}: tile {tile}, plane pad {pad} ({pad_rates}), timing {steps} steps")
     lat.step(warmup)
     torch.cuda.synchronize()
