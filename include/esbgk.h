@@ -197,6 +197,10 @@ int esbgk_set_walls(esbgk_t *h, const double *bottom, const double *top);
  * checkpoint.  Synchronous. */
 int esbgk_set_open_x(esbgk_t *h, int on);
 
+/* Plane padding of the handle's storage in bytes (set at creation, or
+ * chosen by esbgk_autotune for library-owned storage). */
+int esbgk_plane_pad(const esbgk_t *h, int64_t *bytes);
+
 /* Steps taken since init (or loaded from a checkpoint). */
 int esbgk_step_count(const esbgk_t *h, int64_t *n);
 
@@ -252,11 +256,17 @@ int esbgk_get_tile(const esbgk_t *h, int parity, int *block, int *order, int *po
 /* Autotune the launch shape of each parity: if cache_path names a file
  * holding entries for this lattice, N_f class, storage and size class, apply
  * them; otherwise time every candidate (block 128/256/512 x both orders x
- * both policies x 1/4/16 chunks per work-group; each launch timed alone) on
- * the handle's own state, restore that state bitwise, apply the fastest
- * shape per parity and append both to cache_path (if not NULL).  budget_ms
- * bounds the timing (<= 0: no bound).  Needs a second copy of the
- * population storage on the device while it runs.  Synchronous. */
+ * cache policies 1-3 x 1/4/16 chunks per work-group; each launch timed
+ * alone) on the handle's own state, apply the fastest shape per parity and
+ * append both to cache_path (if not NULL).  With library-owned storage
+ * (esbgk_create) it then times plane paddings of 0, 16, 24 and 48 KiB, each
+ * on an allocation of its own, and keeps the fastest allocation: the storage
+ * moves (device addresses change, so capture graphs of esbgk_step after
+ * this call) and the padding goes to the cache too.  Caller-owned storage
+ * keeps its layout.  The handle's state is restored bitwise in any case.
+ * budget_ms bounds the launch-shape timing (<= 0: no bound).  Needs a
+ * second copy of the population storage on the device while it runs, and
+ * for library-owned storage room for two more.  Synchronous. */
 int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
 
 /* Measured ceiling of the step kernels' memory pattern: 74 FP32 planes of

@@ -80,6 +80,7 @@ _sig("esbgk_step", [_vp, ctypes.c_int64])
 _sig("esbgk_set_walls", [_vp, _dp, _dp])
 _sig("esbgk_set_open_x", [_vp, ctypes.c_int])
 _sig("esbgk_step_count", [_vp, _i64p])
+_sig("esbgk_plane_pad", [_vp, _i64p])
 _sig("esbgk_read_moments", [_vp, _dp, _dp, _dp, _dp])
 _sig("esbgk_totals", [_vp, _dp])
 _sig("esbgk_read_cells", [_vp, ctypes.c_int64, _i64p, _dp, _dp])
@@ -163,7 +164,8 @@ class Lattice:
     planes' address streams apart; results do not depend on it."""
 
     def __init__(self, D: int, Q: int, Nf: int, Pr: float, tau: float, dims, storage: str = "f32",
-                 kappa: float = 0.2, device: int = 0, stream=None, streaming: str = "aa", plane_pad: int = 0):
+                 kappa: float = 0.2, device: int = 0, stream=None, streaming: str = "aa", plane_pad: int = 0,
+                 owned: bool = False):
         self.D, self.Q, self.Nf, self.Pr, self.tau = D, Q, Nf, Pr, tau
         self.dims = tuple(int(d) for d in dims)
         if len(self.dims) != D:
@@ -177,12 +179,20 @@ class Lattice:
         self._h = None
         nbytes = storage_bytes(D, Q, Nf, self.dims, storage, streaming, plane_pad)
         self.device = torch.device("cuda", device)
-        self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = _vp()
-        _check(_lib.esbgk_create_ex(D, Q, Nf, Pr, tau, _dims(self.dims), code, self._buf.data_ptr(),
-                                    nbytes, self._stream.cuda_stream, ctypes.byref(h)))
-        self._h = h
+        if owned:
+            # the library allocates (and may move, see autotune) the storage
+            self._buf = None
+            with torch.cuda.device(self.device):
+                _check(_lib.esbgk_create(D, Q, Nf, Pr, tau, _dims(self.dims), code, ctypes.byref(h)))
+            self._h = h
+            _check(_lib.esbgk_set_stream(h, self._stream.cuda_stream))
+        else:
+            self._buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            _check(_lib.esbgk_create_ex(D, Q, Nf, Pr, tau, _dims(self.dims), code, self._buf.data_ptr(),
+                                        nbytes, self._stream.cuda_stream, ctypes.byref(h)))
+            self._h = h
         if kappa != 0.2:
             self.set_kappa(kappa)
 
@@ -200,7 +210,14 @@ class Lattice:
 
     @property
     def storage_tensor(self) -> torch.Tensor:
+        """The caller-owned storage (None when the library owns it)."""
         return self._buf
+
+    @property
+    def plane_pad_bytes(self) -> int:
+        v = ctypes.c_int64()
+        _check(_lib.esbgk_plane_pad(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_kappa(self, kappa: float):
         _check(_lib.esbgk_set_kappa(self._h, kappa))

@@ -636,6 +636,17 @@ int esbgk_set_open_x(esbgk_t *h, int on) {
     return ESBGK_OK;
 }
 
+int esbgk_plane_pad(const esbgk_t *h, int64_t *bytes) {
+    clear_error();
+    if (int rc = check(h)) return rc;
+    if (!bytes) {
+        set_error("bytes is NULL");
+        return ESBGK_EINVAL;
+    }
+    *bytes = (int64_t)h->su.plane_pad;
+    return ESBGK_OK;
+}
+
 int esbgk_step_count(const esbgk_t *h, int64_t *n) {
     clear_error();
     if (int rc = check(h)) return rc;
@@ -1001,8 +1012,37 @@ std::string tune_key(const esbgk_t *h) {
     int sc = 0;
     while ((1ull << (sc + 1)) <= h->su.geom.ncell) sc++;
     char k[128];
-    snprintf(k, sizeof k, "D%dQ%d npop%d st%d log2n%d", h->D, h->Q, h->su.npop, h->storage, sc);
+    snprintf(k, sizeof k, "D%dQ%d npop%d st%d log2n%d", h->D, h->Q, h->su.npop, storage_unpadded(h->storage), sc);
     return k;
+}
+
+// Plane paddings the autotuner times on library-owned storage (bytes).
+constexpr uint64_t kPadCandidates[] = {0, 16384, 24576, 49152};
+
+// Move library-owned storage to a new allocation laid out with plane
+// padding `pad` (the state is copied across).  The old allocation is freed.
+int relayout(esbgk_t *h, uint64_t pad) {
+    DomainSetup nsu = h->su;
+    if (int rc = set_layout(nsu, pad)) return rc;
+    char *nb = nullptr;
+    if (hipError_t e = hipMalloc(&nb, nsu.bytes); e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of %llu bytes failed: %s", (unsigned long long)nsu.bytes, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? ESBGK_ENOMEM : ESBGK_EDEVICE;
+    }
+    int rc = copy_layout(nb, nsu, h->buf, h->su, h->su.copies, hipMemcpyDeviceToDevice, h->stream);
+    if (rc == ESBGK_OK && hipStreamSynchronize(h->stream) != hipSuccess) {
+        set_error("copy to the new layout failed");
+        rc = ESBGK_EDEVICE;
+    }
+    if (rc) {
+        (void)hipFree(nb);
+        return rc;
+    }
+    (void)hipFree(h->buf);
+    h->buf = nb;
+    h->su = nsu;
+    return ESBGK_OK;
 }
 }  // namespace
 
@@ -1014,19 +1054,29 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
         std::ifstream in(cache_path);
         std::string line;
         bool got[2] = {false, false};
+        long long pad = -1;
         while (std::getline(in, line)) {
             if (line.rfind(key + " ", 0) != 0) continue;
             int par, b, o, p, k;
+            long long pd;
             if (sscanf(line.c_str() + key.size(), " parity %d block %d order %d policy %d cpi %d", &par, &b, &o, &p,
                        &k) == 5 &&
                 (par == 0 || par == 1) && esbgk_set_tile(h, par, b, o, p, k) == ESBGK_OK)
                 got[par] = true;
+            else if (sscanf(line.c_str() + key.size(), " plane_pad %lld", &pd) == 1 && pd >= 0)
+                pad = pd;
         }
-        if (got[0] && got[1]) return ESBGK_OK;
+        if (got[0] && got[1] && (!h->owns_buf || pad >= 0)) {
+            clear_error();
+            if (h->owns_buf && (uint64_t)pad != h->su.plane_pad) return relayout(h, (uint64_t)pad);
+            return ESBGK_OK;
+        }
+        clear_error();
     }
     DevTmp save;
     ESBGK_HIP(hipMalloc(&save.p, h->su.bytes));
     ESBGK_HIP(hipMemcpyAsync(save.p, h->buf, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
+    const DomainSetup su_entry = h->su;   // layout of the saved state
     const int64_t steps0 = h->steps;
     const bool from_step0 = h->from_step;
     Events events;
@@ -1073,13 +1123,73 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
                         }
                     }
                 }
-    ESBGK_HIP(hipMemcpyAsync(h->buf, save.p, h->su.bytes, hipMemcpyDeviceToDevice, h->stream));
+    if (!rc) {
+        h->tile[0] = bestt[0];
+        h->tile[1] = bestt[1];
+    }
+    // Library-owned storage: time the plane paddings, each on an allocation
+    // of its own, and keep the fastest allocation (where an allocation lands
+    // in HBM matters as much as the padding itself).
+    if (!rc && h->owns_buf) {
+        auto time_now = [&](double *ms) -> int {
+            h->launch_step();
+            h->launch_step();
+            (void)hipEventRecord(ev[0], h->stream);
+            for (int k = 0; k < 6; k++) h->launch_step();
+            (void)hipEventRecord(ev[1], h->stream);
+            if (int r = launch_error()) return r;
+            float f = 0;
+            if (hipEventSynchronize(ev[1]) != hipSuccess || hipEventElapsedTime(&f, ev[0], ev[1]) != hipSuccess) {
+                set_error("timing events failed");
+                return ESBGK_EDEVICE;
+            }
+            *ms = f;
+            return ESBGK_OK;
+        };
+        double best_ms = 0;
+        rc = time_now(&best_ms);
+        char *best_buf = h->buf;
+        DomainSetup best_su = h->su;
+        const uint64_t pad0 = h->su.plane_pad;
+        for (uint64_t pad : kPadCandidates) {
+            if (rc || pad == pad0) continue;
+            DomainSetup nsu = best_su;
+            if (set_layout(nsu, pad) != ESBGK_OK) {
+                clear_error();
+                continue;
+            }
+            char *nb = nullptr;
+            if (hipMalloc(&nb, nsu.bytes) != hipSuccess) {   // no room for a trial: keep what there is
+                (void)hipGetLastError();
+                break;
+            }
+            rc = copy_layout(nb, nsu, best_buf, best_su, best_su.copies, hipMemcpyDeviceToDevice, h->stream);
+            h->buf = nb;
+            h->su = nsu;
+            double ms = 0;
+            if (!rc) rc = time_now(&ms);
+            (void)hipStreamSynchronize(h->stream);
+            if (!rc && ms < best_ms) {
+                (void)hipFree(best_buf);
+                best_buf = nb;
+                best_su = nsu;
+                best_ms = ms;
+            } else {
+                (void)hipFree(nb);
+                h->buf = best_buf;
+                h->su = best_su;
+            }
+        }
+    }
+    // put the entry state back, in the (possibly new) layout
+    if (int r = copy_layout(h->buf, h->su, (const char *)save.p, su_entry, su_entry.copies,
+                            hipMemcpyDeviceToDevice, h->stream);
+        r && !rc)
+        rc = r;
     ESBGK_HIP(hipStreamSynchronize(h->stream));
     h->steps = steps0;
     h->from_step = from_step0;
     if (rc) return rc;
-    h->tile[0] = bestt[0];
-    h->tile[1] = bestt[1];
     if (cache_path) {
         FILE *fp = std::fopen(cache_path, "a");
         if (!fp) {
@@ -1090,6 +1200,7 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path) {
             std::fprintf(fp, "%s parity %d block %d order %d policy %d cpi %d ms %.4f\n", key.c_str(), par,
                          bestt[par].block, bestt[par].remap ? 2 : 1, bestt[par].policy + 1, bestt[par].cpi,
                          best[par]);
+        if (h->owns_buf) std::fprintf(fp, "%s plane_pad %llu\n", key.c_str(), (unsigned long long)h->su.plane_pad);
         std::fclose(fp);
     }
     return ESBGK_OK;

@@ -135,3 +135,39 @@ def test_benchmark_size_paddings_match_unpadded():
             assert np.array_equal(a, b), pad
         del lat
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("streaming", ["aa", "pull"])
+def test_autotune_chooses_padding_for_library_owned_storage(tmp_path, streaming):
+    """With library-owned storage the autotuner also times plane paddings on
+    allocations of their own and keeps the fastest; the state survives
+    bitwise, later steps equal an untuned caller-owned run, and a second
+    handle takes the padding from the cache."""
+    dims, cache = (256, 96), str(tmp_path / "tune.txt")
+    fields = workloads.random_state(dims, seed=21)
+    ref = esb.Lattice(2, 37, 3, 0.71, 0.7, dims, streaming=streaming)
+    ref.init_fields(*fields)
+    own = esb.Lattice(2, 37, 3, 0.71, 0.7, dims, streaming=streaming, owned=True)
+    assert own.storage_tensor is None and own.plane_pad_bytes == 0
+    own.init_fields(*fields)
+    ref.step(3)
+    own.step(3)
+    own.autotune(cache_path=cache)
+    pad = own.plane_pad_bytes
+    assert pad in (0, 16384, 24576, 49152)
+    assert own.steps == 3
+    assert_same(ref, own)
+    ref.step(4)
+    own.step(4)
+    assert_same(ref, own)
+    with open(cache) as fh:
+        assert any(line.endswith(f"plane_pad {pad}") for line in fh.read().splitlines())
+    second = esb.Lattice(2, 37, 3, 0.71, 0.7, dims, streaming=streaming, owned=True)
+    second.init_fields(*fields)
+    second.autotune(cache_path=cache)
+    assert second.plane_pad_bytes == pad
+    second.step(7)
+    assert_same(ref, second)
+    # caller-owned storage keeps its layout
+    ref.autotune()
+    assert ref.plane_pad_bytes == 0
