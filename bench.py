@@ -434,6 +434,26 @@ def main():
     ceiling = esb.stream_ceiling(N * N, 10)
     roof["measured_stream_ceiling_GBs"] = round(ceiling, 1)
     roof["frac_of_measured_ceiling"] = round(roof["achieved"] / ceiling, 4)
+    # the same probe for the variants' own stream patterns (4-byte planes in
+    # one or two sets; 2^24 cells each): their HBM rate as a fraction of it
+    patterns = {"d2q37_4096_f32_pr0.5": None, "d2q37_4096_f32_pr2": None,
+                "d2q37_4096_f16_dev": (37, 1), "d2q37_4096_bf16_dev": (37, 1), "d3q39_256cube_f32": (78, 2),
+                "d3q39_256cube_bf16": (39, 1), "d2q33_4096_f32": (66, 2)}
+    probed = {(74, 2): ceiling}
+    aa = var.get("d2q37_4096_f32_aa_in_place")
+    if aa is not None:
+        for kern in ("even_kernel", "odd_kernel"):
+            aa[kern]["frac_of_measured_ceiling"] = round(aa[kern]["frac_of_hbm_peak"] * HBM_PEAK_GBS / ceiling, 4)
+    for name, pat in patterns.items():
+        v = var.get(name)
+        if v is None or "roofline_frac" not in v:
+            continue
+        pat = pat or (74, 2)
+        if pat not in probed:
+            log(f"stream ceiling, {pat[0]} planes in {pat[1]} set(s)")
+            probed[pat] = esb.stream_ceiling(N * N, 10, planes=pat[0], sets=pat[1])
+        v["measured_stream_ceiling_GBs"] = round(probed[pat], 1)
+        v["frac_of_measured_ceiling"] = round(v["roofline_frac"] * HBM_PEAK_GBS / probed[pat], 4)
 
     if not args.no_cpu:
         log("cpu baseline (FP64 oracle on the host)")

@@ -281,6 +281,13 @@ int esbgk_autotune(esbgk_t *h, double budget_ms, const char *cache_path);
  * reference next to the published HBM peak, not part of the scheme. */
 int esbgk_stream_ceiling(int64_t cells, int reps, double *gbps);
 
+/* The same probe for the stream pattern of another lattice or storage mode:
+ * `planes` 4-byte planes in `sets` sets (74, 78 or 66 in two sets: FP32 f
+ * and g of D2Q37, D3Q39, D2Q33; 37, 39 or 33 in one set: FP16/BF16 (f, g)
+ * pairs, or one population).  ESBGK_EINVAL for other patterns, for cells <
+ * 256 and for sets over 4 GiB. */
+int esbgk_stream_ceiling_planes(int64_t cells, int planes, int sets, int reps, double *gbps);
+
 /* Release the handle and the memory the library owns.  NULL is a no-op. */
 void esbgk_destroy(esbgk_t *h);
 

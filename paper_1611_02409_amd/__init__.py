@@ -94,14 +94,15 @@ _sig("esbgk_get_tile", [_vp, ctypes.c_int, _ip, _ip, _ip, _ip])
 _sig("esbgk_autotune", [_vp, ctypes.c_double, ctypes.c_char_p])
 _sig("esbgk_destroy", [_vp], None)
 _sig("esbgk_stream_ceiling", [ctypes.c_int64, ctypes.c_int, _dp])
+_sig("esbgk_stream_ceiling_planes", [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp])
 
 
-def stream_ceiling(cells: int = 4096 * 4096, reps: int = 10) -> float:
-    """GB/s (read plus written) of an arithmetic-free read and write of 74
-    FP32 planes of `cells` cells: the best over buffer placements,
-    occupancies, store cache policies and plane strides."""
+def stream_ceiling(cells: int = 4096 * 4096, reps: int = 10, planes: int = 74, sets: int = 2) -> float:
+    """GB/s (read plus written) of an arithmetic-free read and write of
+    `planes` 4-byte planes (in `sets` sets) of `cells` cells: the best over
+    buffer placements, occupancies, store cache policies and plane strides."""
     out = ctypes.c_double()
-    _check(_lib.esbgk_stream_ceiling(int(cells), int(reps), ctypes.byref(out)))
+    _check(_lib.esbgk_stream_ceiling_planes(int(cells), int(planes), int(sets), int(reps), ctypes.byref(out)))
     return out.value
 
 

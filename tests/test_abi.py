@@ -156,3 +156,8 @@ def test_stream_ceiling_rejects_bad_sizes_without_a_device(esb):
     for cells, reps in ((100, 1), (1 << 30, 1), (1 << 20, 0)):
         assert lib.esbgk_stream_ceiling(cells, reps, ctypes.byref(out)) == -1
     assert lib.esbgk_stream_ceiling(1 << 20, 1, None) == -1
+    for planes, sets in ((74, 1), (37, 2), (40, 2), (0, 1)):
+        assert lib.esbgk_stream_ceiling_planes(1 << 20, planes, sets, 1, ctypes.byref(out)) == -1
+        assert "planes" in lib.esbgk_last_error().decode()
+    # a set over 4 GiB
+    assert lib.esbgk_stream_ceiling_planes(30000000, 78, 2, 1, ctypes.byref(out)) == -1

@@ -16,3 +16,9 @@ def test_ceiling_probe_runs_and_is_below_peak():
     assert 1000.0 < big < 8000.0
     small = esb.stream_ceiling(1 << 16, 2)
     assert small > 0.0
+
+
+@pytest.mark.parametrize("planes,sets", [(78, 2), (66, 2), (37, 1), (39, 1), (33, 1)])
+def test_ceiling_probe_other_patterns(planes, sets):
+    rate = esb.stream_ceiling(1 << 22, 2, planes=planes, sets=sets)
+    assert 100.0 < rate < 20000.0
