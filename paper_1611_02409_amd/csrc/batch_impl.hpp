@@ -7,12 +7,14 @@
 // Persistent mode: one launch of co-resident work-groups loops over windows
 // of W steps; inside a window it takes one domain group at a time through
 // its W steps.  Each (group, step) is split over the work-groups by a
-// grid-stride loop over the group's tiles and closed by a grid-wide barrier:
-// every wave drains its stores, the work-group's first thread writes back
-// the XCD's L2 (release at device scope), arrives on a global counter and
-// polls it with relaxed loads; once all work-groups have arrived it
-// invalidates its caches (acquire) once.  A-A streaming needs exactly this
-// ordering between consecutive steps of one domain.  The wait is bounded by
+// launch-wide ticket counter over the group's tiles and closed by a
+// grid-wide barrier: every wave drains its stores, the work-group's first
+// thread writes back the XCD's L2 (release at device scope), arrives on a
+// global counter and polls it with relaxed loads; once all work-groups have
+// arrived it invalidates its caches (acquire) once.  Both streaming schemes
+// (A-A in place, two-copy pull) need exactly this ordering between
+// consecutive steps of one domain: a step reads what the neighbouring tiles
+// wrote in the step before.  The wait is bounded by
 // the shader clock; a timeout sets a status flag, and every work-group that
 // sees the flag leaves, so the launch always drains.
 #pragma once
