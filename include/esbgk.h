@@ -126,9 +126,10 @@ int esbgk_params(int D, int N_f, double Pr, double tau, double kappa, double out
 /* Create a periodic lattice of dims[0] x dims[1] (x dims[2]) cells.
  * Requires every dim >= the lattice reach and few enough cells that one
  * population set fits in 4 GiB (see Storage above; ESBGK_EUNSUPPORTED
- * otherwise, with the largest cell count in the message).  The library allocates the
- * population storage (2 Q planes, or Q when N_f = 0) and owns it; work goes
- * to the default HIP stream until esbgk_set_stream.  The handle starts
+ * otherwise, with the largest cell count in the message).  The library
+ * allocates the population storage (2 Q planes, or Q when N_f = 0) and owns
+ * it (esbgk_autotune may move it to an allocation with another plane
+ * padding); work goes to the default HIP stream until esbgk_set_stream.  The handle starts
  * without a state: call esbgk_init_fields before stepping. */
 int esbgk_create(int D, int Q, int N_f, double Pr, double tau, const int64_t *dims, int storage, esbgk_t **out);
 
