@@ -211,17 +211,18 @@ __device__ __forceinline__ void ld_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, 
 template <int S, int CP = 0>
 __device__ __forceinline__ void st_pair(float f, float g, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     static_assert(S != ST_F32, "paired elements hold 2-byte values");
-    uint32_t lo, hi;
+    uint32_t v;
     if constexpr (S == ST_F16) {
         asm("" : "+v"(f));   // see st
         asm("" : "+v"(g));
-        lo = __half_as_ushort(__float2half_rn(f));
-        hi = __half_as_ushort(__float2half_rn(g));
+        v = uint32_t(__half_as_ushort(__float2half_rn(f))) | (uint32_t(__half_as_ushort(__float2half_rn(g))) << 16);
     } else {
-        lo = __bfloat16_as_ushort(__float2bfloat16(f));
-        hi = __bfloat16_as_ushort(__float2bfloat16(g));
+        // both halves in one packed round-to-nearest-even conversion
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        v = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){f, g}, bf16x2));
     }
-    __builtin_amdgcn_raw_buffer_store_b32(lo | (hi << 16), r, (int)off, (int)soff, CP);
+    __builtin_amdgcn_raw_buffer_store_b32(v, r, (int)off, (int)soff, CP);
 }
 
 // The two population sets of a domain as buffer resources.  With paired
