@@ -211,14 +211,15 @@ __device__ __forceinline__ void ld_pair(__amdgpu_buffer_rsrc_t r, uint32_t off, 
 template <int S, int CP = 0>
 __device__ __forceinline__ void st_pair(float f, float g, __amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
     static_assert(S != ST_F32, "paired elements hold 2-byte values");
+    // both halves in one packed round-to-nearest-even conversion
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
     uint32_t v;
     if constexpr (S == ST_F16) {
         asm("" : "+v"(f));   // see st
         asm("" : "+v"(g));
-        v = uint32_t(__half_as_ushort(__float2half_rn(f))) | (uint32_t(__half_as_ushort(__float2half_rn(g))) << 16);
+        typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+        v = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){f, g}, f16x2));
     } else {
-        // both halves in one packed round-to-nearest-even conversion
-        typedef float f32x2 __attribute__((ext_vector_type(2)));
         typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
         v = __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){f, g}, bf16x2));
     }
