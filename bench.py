@@ -109,6 +109,43 @@ def time_single(esb, torch, D, Q, Nf, Pr, tau, dims, storage, fields, steps, war
                 even_ms=float(np.mean(even)), launch_ms=float(np.mean(per)))
 
 
+GOLDEN_4096 = os.path.join(ROOT, "tests", "golden", "ref_waves4096_pr0.71.npz")
+
+
+def error_vs_fp64(lat, fields, steps=1000):
+    """The stated error of a 4096^2 D2Q37 waves run (N_f = 3, Pr = 0.71,
+    tau = 0.6): relative L2 of rho, u and T, as 512^2 block means, after
+    `steps` steps from the initial state, against the stored FP64 oracle run
+    of the same workload (tests/golden, written by a script that calls only
+    the oracle), and the relative drift of the FP64 totals of mass and
+    energy.  None if the reference is missing."""
+    import workloads
+    if not os.path.exists(GOLDEN_4096):
+        return None
+    ref = np.load(GOLDEN_4096)
+    if f"rho_{steps}" not in ref.files:
+        return None
+    out_n = int(ref["out_n"])
+
+    def rel_l2(a, b):
+        return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+    lat.init_fields(*fields)
+    t0 = lat.totals()
+    lat.step(steps)
+    t1 = lat.totals()
+    m = lat.read_moments()
+    bm = lambda a: workloads.block_mean(a, out_n)
+    e_rho = rel_l2(1.0 + bm(m["rho"] - 1.0), 1.0 + ref[f"rho_{steps}"].astype(np.float64))
+    e_T = rel_l2(1.0 + bm(m["T"] - 1.0), 1.0 + ref[f"T_{steps}"].astype(np.float64))
+    e_u = rel_l2(np.stack([bm(m["u"][0]), bm(m["u"][1])]),
+                 np.stack([ref[f"ux_{steps}"], ref[f"uy_{steps}"]]).astype(np.float64))
+    return {"steps": steps, "reference": "FP64 oracle, 512^2 block means", "rho": float(f"{e_rho:.3g}"),
+            "u": float(f"{e_u:.3g}"), "T": float(f"{e_T:.3g}"),
+            "mass_drift": float(f"{abs(t1[0] - t0[0]) / t0[0]:.3g}"),
+            "energy_drift": float(f"{abs(t1[-1] - t0[-1]) / t0[-1]:.3g}")}
+
+
 def roofline(bytes_per_launch, launch_ms, peak=HBM_PEAK_GBS, traffic=None):
     ach = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(ach, 1), "peak": peak, "unit": "GB/s", "frac": round(ach / peak, 4),
@@ -427,6 +464,24 @@ def main():
         torch.cuda.empty_cache()
     if var:
         out["variants"] = var
+
+    # the stated error of the 4096^2 runs against the FP64 oracle, after the
+    # timed work (fresh lattices: results do not depend on the launch shape
+    # or the plane padding)
+    fields = workloads.waves_noise_2d(N)
+    for storage in ("f32", "f16", "bf16"):
+        if storage != "f32" and storage not in variants:
+            continue
+        log(f"error of the {storage} run against the FP64 oracle (1000 steps)")
+        lat = esb.Lattice(D, Q, Nf, Pr, tau, (N, N), storage=storage, streaming="pull")
+        err = error_vs_fp64(lat, fields)
+        if storage == "f32":
+            out["error_vs_fp64"] = err
+        else:
+            var[f"d2q37_4096_{storage}_dev"]["error_vs_fp64"] = err
+        del lat
+        torch.cuda.empty_cache()
+    del fields
 
     # the arithmetic-free copy kernel of the same pattern, last: its buffer is
     # allocated and freed outside the timed lattices

@@ -33,5 +33,9 @@ def test_bench_prints_one_json_line():
     roof = d["roofline"]
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert 0 < roof["frac"] < 1 and abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
+    # the stated error of the FP32 run against the FP64 oracle (1000 steps)
+    err = d["error_vs_fp64"]
+    assert err is not None and err["steps"] == 1000
+    assert err["rho"] < 1e-5 and err["u"] < 1e-5 and err["T"] < 1e-5
     # MLUPS and the roofline come from the same launches: 592 bytes per cell-step
     assert abs(d["value"] * 1e6 * 592 / 1e9 - roof["achieved"]) / roof["achieved"] < 0.05
