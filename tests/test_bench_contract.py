@@ -13,6 +13,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 
 import bench  # noqa: E402
+import numpy as np  # noqa: E402
 
 NCELL = 4096 * 4096
 
@@ -73,3 +74,41 @@ def test_ingest_scales_by_the_copy_kernel(tmp_path, monkeypatch):
     with open(bench.traffic_path("D2Q37"), "w") as fh:
         json.dump(d, fh)
     assert bench.measured_traffic("pull", (512, 1, 3, 1)) is None
+
+
+class _FakeLattice:
+    """Stands in for a 4096^2 lattice: its moments after `steps` are the
+    stored FP64 reference's block means repeated over 8 x 8 cells, plus a
+    chosen relative perturbation of u; its totals drift by a chosen amount."""
+
+    def __init__(self, ref, du=0.0, drift=0.0):
+        self.ref, self.du, self.drift = ref, du, drift
+
+    def init_fields(self, *fields):
+        self.t = np.array([4096.0 ** 2, 0.0, 0.0, 3.0 * 4096 ** 2])
+
+    def totals(self):
+        return self.t.copy()
+
+    def step(self, n):
+        self.t = self.t * (1.0 + self.drift)
+
+    def read_moments(self):
+        up = lambda a: np.repeat(np.repeat(a.astype(np.float64), 8, axis=0), 8, axis=1)
+        r = self.ref
+        return {"rho": 1.0 + up(r["rho_1000"]), "T": 1.0 + up(r["T_1000"]),
+                "u": (1.0 + self.du) * np.stack([up(r["ux_1000"]), up(r["uy_1000"])])}
+
+
+@pytest.mark.skipif(not os.path.exists(bench.GOLDEN_4096), reason="reference not generated")
+def test_error_vs_fp64_arithmetic():
+    """The bench's error report against the stored FP64 oracle run: zero for
+    the reference itself, the chosen relative error of u and the chosen
+    drift otherwise (block means of repeated values are exact)."""
+    ref = np.load(bench.GOLDEN_4096)
+    e = bench.error_vs_fp64(_FakeLattice(ref), ())
+    assert e["rho"] == 0 and e["u"] == 0 and e["T"] == 0 and e["mass_drift"] == 0
+    e = bench.error_vs_fp64(_FakeLattice(ref, du=1e-3, drift=2e-9), ())
+    assert e["u"] == pytest.approx(1e-3, rel=1e-6)
+    assert e["rho"] < 1e-15 and e["T"] < 1e-15
+    assert e["mass_drift"] == pytest.approx(2e-9, rel=1e-3) and e["energy_drift"] == pytest.approx(2e-9, rel=1e-3)
